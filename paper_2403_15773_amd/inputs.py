@@ -1,0 +1,110 @@
+"""Seeded synthetic inputs shared by the GPU path, its tests and the oracle.
+
+This module holds no arithmetic of the lattice Boltzmann method: it draws
+initial fields (a spherical droplet with a tanh profile, velocity noise, a
+quiescent jet domain) and describes workloads as plain parameter sets.  The
+same arrays are handed to the GPU library and to the oracle.
+
+Noise is a counter-based generator, the SplitMix64 finaliser of
+(key XOR counter) with key = SplitMix64(seed) (Steele, Lea and Flood, 2014),
+so every value is a pure function of (seed, stream, step, node, component):
+  counter = stream * 2**62 + step * 2**32 + node * 4 + comp,
+  xi      = (top 24 bits) * 2**-23 - 1  in [-1, 1), exact in float32.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+
+BC_PERIODIC, BC_FREESLIP, BC_INLET, BC_OUTFLOW, BC_NOSLIP = 0, 1, 2, 3, 4
+
+
+def _finalise(z):
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def splitmix64_next(state):
+    """First SplitMix64 output of ``state``."""
+    with np.errstate(over="ignore"):
+        return _finalise(np.asarray(state, dtype=np.uint64) + _GOLDEN)
+
+
+def noise(seed, stream, step, node, comp):
+    """Uniform xi in [-1, 1) (float64 holding a float32-exact value)."""
+    key = splitmix64_next(np.uint64(seed))
+    node = np.asarray(node, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        ctr = ((np.uint64(stream) << np.uint64(62)) + (np.uint64(step) << np.uint64(32))
+               + (node << np.uint64(2)) + np.uint64(comp))
+    h = _finalise(key ^ ctr)
+    return (h >> np.uint64(40)).astype(np.float64) * (1.0 / 8388608.0) - 1.0
+
+
+def grid_coords(nx, ny, nz):
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return x, y, z
+
+
+def quiescent(nx, ny, nz, phi=0.0):
+    """rho = 1, u = 0, P = 0, phi = const (physical fields, SoA, shape (.., nz, ny, nx))."""
+    sh = (nz, ny, nx)
+    return {"rho": np.ones(sh), "u": np.zeros((3,) + sh), "P": np.zeros((6,) + sh),
+            "phi": np.full(sh, float(phi))}
+
+
+def droplet(n, radius, width=3.0, noise_amp=1e-3, seed=1, stream=0, center=None, rho_inside=None):
+    """Periodic n^3 box with one droplet: phi = (1 - tanh(2 (r - R) / W)) / 2.
+
+    r is the minimum-image distance to ``center`` (default (n/2, n/2, n/2)).
+    u_a = noise_amp * xi(seed, stream, step 0, node, a); rho = 1 (or a
+    pressure-balanced rho if ``rho_inside`` gives the inside excess rho - 1);
+    P = 0.
+    """
+    if center is None:
+        center = (n / 2.0, n / 2.0, n / 2.0)
+    x, y, z = grid_coords(n, n, n)
+    d = []
+    for c, v in zip(center, (x, y, z)):
+        dv = v - c
+        dv = dv - n * np.round(dv / n)
+        d.append(dv)
+    r = np.sqrt(d[0] ** 2 + d[1] ** 2 + d[2] ** 2)
+    phi = 0.5 * (1.0 - np.tanh(2.0 * (r - radius) / width))
+    node = (x + n * (y + n * z)).astype(np.uint64)
+    u = np.stack([noise_amp * noise(seed, stream, 0, node, a) for a in range(3)])
+    rho = np.ones_like(phi)
+    if rho_inside is not None:
+        rho = 1.0 + rho_inside * (phi - phi.mean())
+    return {"rho": rho, "u": u, "P": np.zeros((6,) + phi.shape), "phi": phi}
+
+
+# ---- workloads: plain parameter sets in lattice units ----
+
+def droplet_params(n=32, nu=0.01, sigma=0.01, width=3.0):
+    return dict(nx=n, ny=n, nz=n, nu=nu, sigma=sigma, width=width, bc=(BC_PERIODIC,) * 6)
+
+
+def jet_params(nx, ny, nz, d, u, re, we, width=3.0, noise=0.01, seed=2):
+    """Round jet: inlet disc on z = 0, outflow at z = nz-1, free-slip lateral walls.
+    Re = U D / nu and We = rho U^2 D / sigma with rho = 1."""
+    return dict(nx=nx, ny=ny, nz=nz, nu=u * d / re, sigma=u * u * d / we, width=width,
+                bc=(BC_FREESLIP, BC_FREESLIP, BC_FREESLIP, BC_FREESLIP, BC_INLET, BC_OUTFLOW),
+                inlet_u=u, inlet_d=d, inlet_noise=noise, seed=seed)
+
+
+WORKLOADS = {
+    # 32^3 periodic droplet, R = 8, W = 3, nu = 0.01, sigma = 0.01, 200 steps
+    "droplet32": dict(params=droplet_params(32), steps=200, init="droplet"),
+    # 128x128x512 round jet, D = 20, U = 0.05, Re = 5000, We = 100, 2000 steps
+    "jet128": dict(params=jet_params(128, 128, 512, d=20, u=0.05, re=5000, we=100, seed=2), steps=2000,
+                   init="quiescent"),
+    # 512x512x2048 round jet, D = 40, U = 0.05, Re = 5000, We = 2000, 200 warm-up + 500 timed
+    "jet512": dict(params=jet_params(512, 512, 2048, d=40, u=0.05, re=5000, we=2000, seed=3), steps=500,
+                   init="quiescent"),
+}
