@@ -1,0 +1,165 @@
+/*
+ * tslb.h -- C-ABI of the MI355X (gfx950) multicomponent thread-safe lattice
+ * Boltzmann (TSLB) time step.
+ *
+ * The method is that of Montessori, Hegele Jr. and Lauricella, "A
+ * high-performance lattice Boltzmann model for multicomponent turbulent jet
+ * simulations" (arXiv:2403.15773):
+ *   - hydrodynamics on D3Q27, stored as moments (density, velocity and the
+ *     non-equilibrium momentum flux) instead of populations (Methodology, the
+ *     paragraph after Eq. 7); each step rebuilds the post-collision populations
+ *     from the neighbours' moments and sums them into the node (Eqs. 5, 6, 8 and
+ *     the thread-safe sketch), with the third-order Hermite equilibrium (Eq. 16)
+ *     and third-order regularised non-equilibrium part (Eqs. 18, 19);
+ *   - surface tension by the continuum-surface force F = -sigma kappa grad(phi)
+ *     (Eqs. 20, 21), entered with Guo's forcing;
+ *   - the phase field on D3Q7 with a first-order equilibrium, unit relaxation and
+ *     the anti-diffusion source (Eqs. 22-24);
+ *   - boundaries by imposing density and/or velocity on one-node boundary layers
+ *     and copying the non-equilibrium part from the nearest interior node
+ *     (Eqs. 9, 10).
+ *
+ * Conventions shared by every call:
+ *   - Every function returns an int status (TSLB_OK or a negative TSLB_E_*);
+ *     nothing throws across this interface.  tslb_last_error() gives the text.
+ *   - A context is used by one host thread at a time.  Work is queued on the
+ *     context's HIP stream; calls that hand results to the host synchronise it.
+ *   - Host arrays are owned by the caller and hold exactly N = nx*ny*nz values
+ *     per component, structure of arrays, x fastest: value (x, y, z) of
+ *     component c at [c*N + x + nx*(y + ny*z)].  Symmetric tensors use the
+ *     component order xx, yy, zz, xy, xz, yz.
+ *   - Device memory is owned by the context unless the caller passes
+ *     device_buffer, which must then stay allocated until tslb_destroy().
+ */
+#ifndef TSLB_H
+#define TSLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TSLB_ABI_VERSION 1
+
+enum {
+    TSLB_OK = 0,
+    TSLB_E_INVAL = -1,    /* bad argument or parameter set */
+    TSLB_E_NOMEM = -2,    /* device or host allocation failed, or budget exceeded */
+    TSLB_E_DEVICE = -3,   /* a HIP call failed */
+    TSLB_E_UNSTABLE = -4, /* a non-finite value appeared; state kept at the failing step */
+    TSLB_E_STATE = -5     /* call out of order (e.g. step before any state was set) */
+};
+
+/* Face rules (faces in the order -x, +x, -y, +y, -z, +z). */
+enum {
+    TSLB_BC_PERIODIC = 0, /* both faces of the axis must be periodic */
+    TSLB_BC_FREESLIP = 1, /* normal velocity and normal-tangential stress zero; rest copied */
+    TSLB_BC_INLET = 2,    /* -z face only: round nozzle, u_z = U s(r)(1 + a xi), phi = s(r) */
+    TSLB_BC_OUTFLOW = 3,  /* density 1; velocity, stress and phase copied */
+    TSLB_BC_NOSLIP = 4    /* velocity zero; rest copied */
+};
+
+/* Storage type of the ten moment planes (phi is always binary32). */
+enum {
+    TSLB_STORE_FP32 = 0,
+    TSLB_STORE_FP16 = 1, /* scaled deviations rho'/U^2, ubar/U, Q/U^2, round to nearest even */
+    TSLB_STORE_BF16 = 2
+};
+
+typedef struct tslb_ctx tslb_ctx;
+
+typedef struct tslb_params {
+    int32_t abi_version;     /* must equal TSLB_ABI_VERSION */
+    int32_t nx, ny, nz;      /* lattice size; each >= 4 on a non-periodic axis, >= 1 otherwise */
+    int32_t bc[6];           /* TSLB_BC_* for faces -x,+x,-y,+y,-z,+z */
+    double nu;               /* kinematic viscosity > 0; omega = 1/(3 nu + 1/2) < 2 (Eqs. 3-4) */
+    double sigma;            /* surface tension >= 0 (Eq. 20) */
+    double width;            /* interface width W > 0 */
+    double gamma;            /* anti-diffusion constant of Eq. 24; <= 0 selects 2/W */
+    double eps;              /* n = G/(|G| + eps) (Eq. 21); < 0 selects the default 1e-4 */
+    double inlet_u;          /* nozzle velocity U (TSLB_BC_INLET) */
+    double inlet_d;          /* nozzle diameter D; axis at ((nx-1)/2, (ny-1)/2) */
+    double inlet_noise;      /* relative amplitude a of the inlet perturbation */
+    uint64_t seed;           /* key of the counter-based inlet noise */
+    int32_t storage;         /* TSLB_STORE_* */
+    double u_scale;          /* U of the scaled-deviation storage; <= 0 selects 0.05 */
+    int32_t check_interval;  /* steps between finite/mass checks inside tslb_step; 0 = never */
+    int32_t device;          /* HIP device ordinal */
+    void *device_buffer;     /* optional caller-owned device allocation for the state */
+    size_t device_buffer_bytes;
+    void *stream;            /* optional hipStream_t; NULL = the context creates its own */
+} tslb_params;
+
+/* Fill *p with defaults: periodic 32^3, nu = 0.1, sigma = 0, W = 3, FP32. */
+void tslb_params_init(tslb_params *p);
+
+/* sizeof(tslb_params) as compiled into the library (binding layout check). */
+size_t tslb_params_size(void);
+
+/* Bytes of device memory the state needs (two buffers); the size device_buffer
+ * must have.  0 if the parameters are invalid. */
+size_t tslb_required_bytes(const tslb_params *p);
+
+/* Validate p, derive omega and gamma, allocate (or adopt) device memory and bind
+ * the stream.  On success *out owns the context. */
+int tslb_create(const tslb_params *p, tslb_ctx **out);
+
+/* Set the state at step `step` from physical host fields: rho_dev = rho - 1
+ * (N; the deviation, because binary32 cannot resolve small density changes
+ * around 1), u (3N), pi_neq (6N: the Guo-corrected non-equilibrium momentum
+ * flux P), phi (N).  The stored raw state is rho - 1, ubar = u - F/(2 rho),
+ * Q = P - F F/(4 rho) and phi rounded to the fixed-point grid 2^-30 (clamped to
+ * [-0.45, 1.45]), with F computed from that phi.  Synchronises. */
+int tslb_set_state(tslb_ctx *ctx, const float *rho_dev, const float *u, const float *pi_neq, const float *phi,
+                   int64_t step);
+
+/* Queue nsteps fused steps (asynchronous unless check_interval triggers a
+ * check, which synchronises and returns TSLB_E_UNSTABLE on a non-finite value). */
+int tslb_step(tslb_ctx *ctx, int64_t nsteps);
+
+/* Wait for queued work. */
+int tslb_sync(tslb_ctx *ctx);
+
+/* Physical moments at the current step: rho_dev = rho - 1 (N), u (3N),
+ * pi_neq (6N); any pointer may be NULL.  Synchronises. */
+int tslb_moments(tslb_ctx *ctx, float *rho_dev, float *u, float *pi_neq);
+
+/* Phase field phi (N) at the current step.  Synchronises. */
+int tslb_phase(tslb_ctx *ctx, float *phi);
+
+/* Raw state as stored (bitwise checkpoint): bytes must equal tslb_state_bytes(). */
+size_t tslb_state_bytes(const tslb_ctx *ctx);
+int tslb_get_state_raw(tslb_ctx *ctx, void *host, size_t bytes);
+int tslb_set_state_raw(tslb_ctx *ctx, const void *host, size_t bytes, int64_t step);
+
+/* Conservation diagnostics of the current state: mass = sum rho (binary32
+ * compensated sums per thread, binary64 across threads), phase = sum phi (exact
+ * integer sum of the fixed-point field, returned as binary64), the current step
+ * index and whether every stored moment is finite.  Synchronises. */
+int tslb_diagnostics(tslb_ctx *ctx, double *mass, double *phase_sum, int64_t *step, int32_t *finite);
+
+/* Current step index (no synchronisation). */
+int64_t tslb_step_index(const tslb_ctx *ctx);
+
+/* Enable (1) or disable (0) per-launch HIP-event timing of the fused step
+ * kernel on the context's stream.  Off by default. */
+int tslb_set_timing(tslb_ctx *ctx, int enable);
+
+/* Average duration in milliseconds of one fused step-kernel launch over the
+ * last tslb_step() call made with timing enabled; synchronises.  Returns 0 if
+ * no timed launch exists. */
+double tslb_last_step_kernel_ms(tslb_ctx *ctx);
+
+/* Release the context and everything it allocated. */
+void tslb_destroy(tslb_ctx *ctx);
+
+/* Text of the last error of ctx, or of the calling thread when ctx is NULL. */
+const char *tslb_last_error(const tslb_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSLB_H */

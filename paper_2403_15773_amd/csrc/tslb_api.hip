@@ -1,0 +1,400 @@
+// C-ABI of the TSLB library: context lifetime, state transfer, the step loop
+// and diagnostics.  Declarations and contracts are in include/tslb.h.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "tslb_internal.h"
+
+using namespace tslb;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+int fail(tslb_ctx *c, int code, const std::string &msg) {
+    if (c)
+        c->err = msg;
+    else
+        g_thread_error = msg;
+    return code;
+}
+
+#define HIP_TRY(c, expr)                                                                                  \
+    do {                                                                                                  \
+        hipError_t e_ = (expr);                                                                           \
+        if (e_ != hipSuccess)                                                                             \
+            return fail((c), TSLB_E_DEVICE, std::string(#expr) + " failed: " + hipGetErrorString(e_));    \
+    } while (0)
+
+bool axis_ok(int lo, int hi, int n, int axis, std::string &why) {
+    if ((lo == TSLB_BC_PERIODIC) != (hi == TSLB_BC_PERIODIC)) {
+        why = "periodic faces must come in pairs (axis " + std::to_string(axis) + ")";
+        return false;
+    }
+    for (int side = 0; side < 2; ++side) {
+        int b = side ? hi : lo;
+        if (b < TSLB_BC_PERIODIC || b > TSLB_BC_NOSLIP) {
+            why = "unknown boundary rule " + std::to_string(b);
+            return false;
+        }
+        if (b == TSLB_BC_INLET && !(axis == 2 && side == 0)) {
+            why = "the inlet rule is only defined on the -z face";
+            return false;
+        }
+    }
+    if (lo != TSLB_BC_PERIODIC && n < 4) {
+        why = "a non-periodic axis needs at least 4 nodes";
+        return false;
+    }
+    return true;
+}
+
+bool validate(const tslb_params *p, std::string &why) {
+    if (!p) { why = "params is NULL"; return false; }
+    if (p->abi_version != TSLB_ABI_VERSION) { why = "abi_version mismatch"; return false; }
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) { why = "lattice sizes must be positive"; return false; }
+    long long N = (long long)p->nx * p->ny * p->nz;
+    if (N >= (1ll << 31) * 4) { why = "lattice too large"; return false; }
+    if ((long long)p->nx * p->ny >= (1ll << 30)) { why = "inlet plane exceeds the noise counter range"; return false; }
+    const int n[3] = {p->nx, p->ny, p->nz};
+    for (int a = 0; a < 3; ++a)
+        if (!axis_ok(p->bc[2 * a], p->bc[2 * a + 1], n[a], a, why)) return false;
+    if (!(p->nu > 0.0) || !std::isfinite(p->nu)) { why = "nu must be positive"; return false; }
+    if (!(1.0 / (3.0 * p->nu + 0.5) < 2.0)) { why = "omega must stay below 2"; return false; }
+    if (!(p->sigma >= 0.0) || !std::isfinite(p->sigma)) { why = "sigma must be >= 0"; return false; }
+    if (!(p->width > 0.0) || !std::isfinite(p->width)) { why = "width must be positive"; return false; }
+    if (p->storage < TSLB_STORE_FP32 || p->storage > TSLB_STORE_BF16) { why = "unknown storage"; return false; }
+    if (p->check_interval < 0) { why = "check_interval must be >= 0"; return false; }
+    if (p->bc[4] == TSLB_BC_INLET && !(p->inlet_d > 0.0)) { why = "inlet_d must be positive"; return false; }
+    return true;
+}
+
+// Scratch planes used by set-state, readout and the materialised-geometry step.
+int ensure_planes(tslb_ctx *c) {
+    if (c->scratch.stage && c->scratch.geo) return TSLB_OK;
+    size_t ld = (size_t)c->geo.ld;
+    if (!c->scratch.stage) HIP_TRY(c, hipMalloc((void **)&c->scratch.stage, 11 * ld * sizeof(float)));
+    if (!c->scratch.geo) HIP_TRY(c, hipMalloc((void **)&c->scratch.geo, 9 * ld * sizeof(float)));
+    return TSLB_OK;
+}
+
+int fill_boundary_now(tslb_ctx *c) {
+    HIP_TRY(c, launch_boundary(c, c->buf[c->cur], c->step, c->stream));
+    return TSLB_OK;
+}
+
+// out[0] = sum rho', out[1] = finite probe (NaN iff a stored moment is not finite),
+// *phi_fixed = exact sum of the fixed-point phase field.
+int run_diagnostics(tslb_ctx *c, double out[2], long long *phi_fixed) {
+    HIP_TRY(c, launch_diagnostics(c, c->buf[c->cur], c->scratch, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(out, c->scratch.result, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(phi_fixed, c->scratch.result_i, sizeof(long long), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TSLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tslb_params_init(tslb_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->abi_version = TSLB_ABI_VERSION;
+    p->nx = p->ny = p->nz = 32;
+    p->nu = 0.1;
+    p->sigma = 0.0;
+    p->width = 3.0;
+    p->gamma = 0.0;
+    p->eps = -1.0;
+    p->storage = TSLB_STORE_FP32;
+    p->u_scale = 0.0;
+}
+
+size_t tslb_params_size(void) { return sizeof(tslb_params); }
+
+size_t tslb_required_bytes(const tslb_params *p) {
+    std::string why;
+    if (!validate(p, why)) return 0;
+    long long N = (long long)p->nx * p->ny * p->nz;
+    return 2 * state_buffer_bytes(N, p->storage);
+}
+
+int tslb_create(const tslb_params *p, tslb_ctx **out) {
+    if (!out) return fail(nullptr, TSLB_E_INVAL, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    if (!validate(p, why)) return fail(nullptr, TSLB_E_INVAL, why);
+    hipError_t e = hipSetDevice(p->device);
+    if (e != hipSuccess) return fail(nullptr, TSLB_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    tslb_ctx *c = new (std::nothrow) tslb_ctx();
+    if (!c) return fail(nullptr, TSLB_E_NOMEM, "host allocation failed");
+    c->p = *p;
+    c->storage = p->storage;
+    Geo &g = c->geo;
+    g.nx = p->nx; g.ny = p->ny; g.nz = p->nz;
+    for (int a = 0; a < 3; ++a) g.per[a] = p->bc[2 * a] == TSLB_BC_PERIODIC;
+    g.N = (long long)p->nx * p->ny * p->nz;
+    g.ld = (long long)plane_elems(g.N);
+    c->has_boundary = !(g.per[0] && g.per[1] && g.per[2]);
+    Phys &ph = c->phys;
+    ph.omega = (float)(1.0 / (3.0 * p->nu + 0.5));
+    ph.sigma = (float)p->sigma;
+    ph.gamma = (float)(p->gamma > 0.0 ? p->gamma : 2.0 / p->width);
+    ph.eps = (float)(p->eps >= 0.0 ? p->eps : 1e-4);
+    ph.width = (float)p->width;
+    ph.inlet_u = (float)p->inlet_u;
+    ph.inlet_d = (float)p->inlet_d;
+    ph.inlet_noise = (float)p->inlet_noise;
+    ph.noise_key = splitmix_finalise(p->seed + 0x9e3779b97f4a7c15ULL);
+    for (int s = 0; s < 6; ++s) ph.bc[s] = p->bc[s];
+    double U = p->u_scale > 0.0 ? p->u_scale : 0.05;
+    if (c->storage == TSLB_STORE_FP32) U = 1.0;
+    c->scales.s1 = (float)U;
+    c->scales.s2 = (float)(U * U);
+    c->scales.inv_s1 = (float)(1.0 / U);
+    c->scales.inv_s2 = (float)(1.0 / (U * U));
+    c->buffer_bytes = state_buffer_bytes(g.N, c->storage);
+    size_t need = 2 * c->buffer_bytes;
+    if (p->device_buffer) {
+        if (p->device_buffer_bytes < need) {
+            delete c;
+            return fail(nullptr, TSLB_E_INVAL, "device_buffer is smaller than tslb_required_bytes()");
+        }
+        if (((uintptr_t)p->device_buffer & 255u) != 0) {
+            delete c;
+            return fail(nullptr, TSLB_E_INVAL, "device_buffer must be 256-byte aligned");
+        }
+        c->base = p->device_buffer;
+        c->owns_base = false;
+    } else {
+        e = hipMalloc(&c->base, need);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(nullptr, TSLB_E_NOMEM, std::string("hipMalloc(state): ") + hipGetErrorString(e));
+        }
+        c->owns_base = true;
+    }
+    size_t esz = c->storage == TSLB_STORE_FP32 ? 4 : 2;
+    size_t mom_bytes = ((size_t)kPlanes * g.ld * esz + 255) / 256 * 256;
+    for (int b = 0; b < 2; ++b) {
+        char *base = (char *)c->base + b * c->buffer_bytes;
+        c->buf[b].mom = base;
+        c->buf[b].phi = (int32_t *)(base + mom_bytes);
+    }
+    if (p->stream) {
+        c->stream = (hipStream_t)p->stream;
+        c->owns_stream = false;
+    } else {
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            tslb_destroy(c);
+            return fail(nullptr, TSLB_E_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        }
+        c->owns_stream = true;
+    }
+    c->scratch.partial_blocks = diagnostics_blocks(c);
+    e = hipMalloc((void **)&c->scratch.partial, c->scratch.partial_blocks * 2 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&c->scratch.partial_i, c->scratch.partial_blocks * sizeof(long long));
+    if (e == hipSuccess) e = hipMalloc((void **)&c->scratch.result, 2 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&c->scratch.result_i, sizeof(long long));
+    if (e == hipSuccess) e = hipMemsetAsync(c->base, 0, need, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        tslb_destroy(c);
+        return fail(nullptr, TSLB_E_DEVICE, std::string("context set-up: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return TSLB_OK;
+}
+
+int tslb_set_state(tslb_ctx *c, const float *rho_dev, const float *u, const float *pi_neq, const float *phi,
+                   int64_t step) {
+    if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    if (!rho_dev || !u || !pi_neq || !phi) return fail(c, TSLB_E_INVAL, "every field is required");
+    if (step < 0) return fail(c, TSLB_E_INVAL, "step must be >= 0");
+    int rc = ensure_planes(c);
+    if (rc) return rc;
+    const size_t N = (size_t)c->geo.N, ld = (size_t)c->geo.ld;
+    float *st = c->scratch.stage;
+    HIP_TRY(c, hipMemcpyAsync(st, rho_dev, N * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpy2DAsync(st + ld, ld * 4, u, N * 4, N * 4, 3, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpy2DAsync(st + 4 * ld, ld * 4, pi_neq, N * 4, N * 4, 6, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(st + 10 * ld, phi, N * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, launch_set_state(c, st, c->scratch.geo, c->buf[c->cur], c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->step = step;
+    c->state_set = true;
+    return TSLB_OK;
+}
+
+int tslb_step(tslb_ctx *c, int64_t nsteps) {
+    if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    if (nsteps < 0) return fail(c, TSLB_E_INVAL, "nsteps must be >= 0");
+    if (!c->state_set) return fail(c, TSLB_E_STATE, "no state: call tslb_set_state first");
+    int rc = ensure_planes(c);
+    if (rc) return rc;
+    StepTimer &tm = c->timer;
+    const size_t max_timed = 8192;
+    size_t timed = 0;
+    if (tm.enabled) {
+        size_t want = (size_t)(nsteps < (int64_t)max_timed ? nsteps : (int64_t)max_timed);
+        while (tm.ev.size() < 2 * want) {
+            hipEvent_t ev;
+            HIP_TRY(c, hipEventCreate(&ev));
+            tm.ev.push_back(ev);
+        }
+        tm.used = 0;
+    }
+    for (int64_t s = 0; s < nsteps; ++s) {
+        HIP_TRY(c, launch_boundary(c, c->buf[c->cur], c->step, c->stream));
+        bool timing = tm.enabled && timed < max_timed;
+        if (timing) HIP_TRY(c, hipEventRecord(tm.ev[2 * timed], c->stream));
+        HIP_TRY(c, launch_step(c, c->buf[c->cur], c->buf[c->cur ^ 1], c->stream));
+        if (timing) {
+            HIP_TRY(c, hipEventRecord(tm.ev[2 * timed + 1], c->stream));
+            ++timed;
+        }
+        c->cur ^= 1;
+        c->step += 1;
+        if (c->p.check_interval > 0 && c->step % c->p.check_interval == 0) {
+            double d[2];
+            long long phi_sum;
+            rc = fill_boundary_now(c);
+            if (rc) return rc;
+            rc = run_diagnostics(c, d, &phi_sum);
+            if (rc) return rc;
+            if (!std::isfinite(d[1])) {
+                tm.used = timed;
+                char msg[160];
+                std::snprintf(msg, sizeof msg, "non-finite state at step %lld", (long long)c->step);
+                return fail(c, TSLB_E_UNSTABLE, msg);
+            }
+        }
+    }
+    if (tm.enabled) tm.used = timed;
+    return TSLB_OK;
+}
+
+int tslb_sync(tslb_ctx *c) {
+    if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TSLB_OK;
+}
+
+int tslb_moments(tslb_ctx *c, float *rho_dev, float *u, float *pi_neq) {
+    if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    if (!c->state_set) return fail(c, TSLB_E_STATE, "no state");
+    int rc = ensure_planes(c);
+    if (rc) return rc;
+    rc = fill_boundary_now(c);
+    if (rc) return rc;
+    const size_t N = (size_t)c->geo.N, ld = (size_t)c->geo.ld;
+    float *st = c->scratch.stage;
+    HIP_TRY(c, launch_geometry(c, c->buf[c->cur].phi, c->scratch.geo, c->stream));
+    HIP_TRY(c, launch_readout(c, c->buf[c->cur], c->scratch.geo, st, c->stream));
+    if (rho_dev) HIP_TRY(c, hipMemcpyAsync(rho_dev, st, N * 4, hipMemcpyDeviceToHost, c->stream));
+    if (u) HIP_TRY(c, hipMemcpy2DAsync(u, N * 4, st + ld, ld * 4, N * 4, 3, hipMemcpyDeviceToHost, c->stream));
+    if (pi_neq)
+        HIP_TRY(c, hipMemcpy2DAsync(pi_neq, N * 4, st + 4 * ld, ld * 4, N * 4, 6, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TSLB_OK;
+}
+
+int tslb_phase(tslb_ctx *c, float *phi) {
+    if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    if (!phi) return fail(c, TSLB_E_INVAL, "phi is NULL");
+    if (!c->state_set) return fail(c, TSLB_E_STATE, "no state");
+    int rc = fill_boundary_now(c);
+    if (rc) return rc;
+    const size_t N = (size_t)c->geo.N;
+    std::vector<int32_t> fixed(N);
+    HIP_TRY(c, hipMemcpyAsync(fixed.data(), c->buf[c->cur].phi, N * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < N; ++i) phi[i] = phi_to_float(fixed[i]);
+    return TSLB_OK;
+}
+
+size_t tslb_state_bytes(const tslb_ctx *c) { return c ? c->buffer_bytes : 0; }
+
+int tslb_get_state_raw(tslb_ctx *c, void *host, size_t bytes) {
+    if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    if (!host || bytes != c->buffer_bytes) return fail(c, TSLB_E_INVAL, "bytes must equal tslb_state_bytes()");
+    if (!c->state_set) return fail(c, TSLB_E_STATE, "no state");
+    int rc = fill_boundary_now(c);
+    if (rc) return rc;
+    HIP_TRY(c, hipMemcpyAsync(host, c->buf[c->cur].mom, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TSLB_OK;
+}
+
+int tslb_set_state_raw(tslb_ctx *c, const void *host, size_t bytes, int64_t step) {
+    if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    if (!host || bytes != c->buffer_bytes) return fail(c, TSLB_E_INVAL, "bytes must equal tslb_state_bytes()");
+    if (step < 0) return fail(c, TSLB_E_INVAL, "step must be >= 0");
+    HIP_TRY(c, hipMemcpyAsync(c->buf[c->cur].mom, host, bytes, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->step = step;
+    c->state_set = true;
+    return TSLB_OK;
+}
+
+int tslb_diagnostics(tslb_ctx *c, double *mass, double *phase_sum, int64_t *step, int32_t *finite) {
+    if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    if (!c->state_set) return fail(c, TSLB_E_STATE, "no state");
+    int rc = fill_boundary_now(c);
+    if (rc) return rc;
+    double d[2];
+    long long phi_fixed = 0;
+    rc = run_diagnostics(c, d, &phi_fixed);
+    if (rc) return rc;
+    if (mass) *mass = (double)c->geo.N + d[0];
+    if (phase_sum) *phase_sum = std::ldexp((double)phi_fixed, -kPhiFrac);
+    if (step) *step = c->step;
+    if (finite) *finite = std::isfinite(d[1]) ? 1 : 0;
+    return TSLB_OK;
+}
+
+int64_t tslb_step_index(const tslb_ctx *c) { return c ? c->step : -1; }
+
+int tslb_set_timing(tslb_ctx *c, int enable) {
+    if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    c->timer.enabled = enable != 0;
+    c->timer.used = 0;
+    return TSLB_OK;
+}
+
+double tslb_last_step_kernel_ms(tslb_ctx *c) {
+    if (!c || c->timer.used == 0) return 0.0;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return 0.0;
+    double total = 0.0;
+    for (size_t k = 0; k < c->timer.used; ++k) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->timer.ev[2 * k], c->timer.ev[2 * k + 1]) != hipSuccess) return 0.0;
+        total += ms;
+    }
+    return total / (double)c->timer.used;
+}
+
+void tslb_destroy(tslb_ctx *c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t ev : c->timer.ev) (void)hipEventDestroy(ev);
+    if (c->scratch.stage) (void)hipFree(c->scratch.stage);
+    if (c->scratch.geo) (void)hipFree(c->scratch.geo);
+    if (c->scratch.partial) (void)hipFree(c->scratch.partial);
+    if (c->scratch.partial_i) (void)hipFree(c->scratch.partial_i);
+    if (c->scratch.result) (void)hipFree(c->scratch.result);
+    if (c->scratch.result_i) (void)hipFree(c->scratch.result_i);
+    if (c->owns_base && c->base) (void)hipFree(c->base);
+    if (c->owns_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char *tslb_last_error(const tslb_ctx *c) { return c ? c->err.c_str() : g_thread_error.c_str(); }
+
+}  // extern "C"

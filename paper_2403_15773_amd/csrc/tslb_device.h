@@ -1,0 +1,140 @@
+// Device-side definitions shared by the HIP kernels of the TSLB library (gfx950).
+//
+// State layout in HBM (one buffer; the library keeps two, A and B):
+//   ten moment planes, each `ld` elements of the storage type T, in the order
+//     0 rho' = rho - 1, 1..3 ubar = j/rho, 4..9 Q = Pi - rho c_s^2 I - j j/rho
+//     (xx, yy, zz, xy, xz, yz),
+//   then one plane of the phase field phi as signed fixed point: int32 with 30
+//   fractional bits (resolution 2^-30 = 9.3e-10, values clamped to
+//   [-0.45, 1.45] so that any difference of two values fits in int32), so that
+//   phi near 1 keeps 64x finer resolution than binary32 and the phase streaming
+//   runs in exact integer arithmetic (the phase sum is conserved bit for bit).
+// Node (x, y, z) sits at element x + nx*(y + ny*z) of every plane.  `ld` is N
+// rounded up to a multiple of 64, so every plane starts 256-byte aligned.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tslb {
+
+constexpr int kPlanes = 10;  // stored moment planes (phi is separate)
+
+// Lattice geometry as the kernels see it.
+struct Geo {
+    int nx, ny, nz;
+    int per[3];      // 1 = periodic axis
+    long long N;     // nx*ny*nz
+    long long ld;    // plane stride in elements
+};
+
+// Physical parameters in binary32.
+struct Phys {
+    float omega;       // 1/(3 nu + 1/2)
+    float sigma;       // surface tension
+    float gamma;       // anti-diffusion constant
+    float eps;         // regulariser of |grad phi|
+    float width;       // interface width W
+    float inlet_u, inlet_d, inlet_noise;
+    unsigned long long noise_key;  // SplitMix64(seed)
+    int bc[6];
+};
+
+// Scaled-deviation storage: value = stored * scale.  FP32 storage uses scale 1.
+struct Scales {
+    float s2, s1;          // U^2 for rho' and Q, U for ubar
+    float inv_s2, inv_s1;
+};
+
+// ---- storage traits -------------------------------------------------------
+
+enum { ST_FP32 = 0, ST_FP16 = 1, ST_BF16 = 2 };
+
+template <int ST> struct Store;
+
+template <> struct Store<ST_FP32> {
+    using T = float;
+    static __device__ __forceinline__ float load(const T *p, long long i, float) { return p[i]; }
+    static __device__ __forceinline__ void store(T *p, long long i, float v, float) { p[i] = v; }
+};
+
+template <> struct Store<ST_FP16> {
+    using T = _Float16;
+    static __device__ __forceinline__ float load(const T *p, long long i, float s) { return (float)p[i] * s; }
+    // the float -> half conversion rounds to nearest even
+    static __device__ __forceinline__ void store(T *p, long long i, float v, float inv_s) { p[i] = (_Float16)(v * inv_s); }
+};
+
+template <> struct Store<ST_BF16> {
+    using T = uint16_t;
+    static __device__ __forceinline__ float load(const T *p, long long i, float s) {
+        return __uint_as_float((uint32_t)p[i] << 16) * s;
+    }
+    // round to nearest even on the upper 16 bits (NaN kept quiet)
+    static __device__ __forceinline__ void store(T *p, long long i, float v, float inv_s) {
+        uint32_t b = __float_as_uint(v * inv_s);
+        uint32_t r = ((b & 0x7fffffffu) > 0x7f800000u) ? (b | 0x00400000u) : (b + 0x7fffu + ((b >> 16) & 1u));
+        p[i] = (uint16_t)(r >> 16);
+    }
+};
+
+// ---- fixed-point phase field ----------------------------------------------
+
+constexpr int kPhiFrac = 30;
+constexpr int32_t kPhiOne = 1 << kPhiFrac;
+constexpr float kPhiUlp = 1.0f / (float)(1 << kPhiFrac);   // 2^-30
+constexpr float kPhiInvUlp = (float)(1 << kPhiFrac);       // 2^30
+constexpr float kPhiMin = -0.45f, kPhiMax = 1.45f;
+
+__host__ __device__ inline float phi_to_float(int32_t v) { return (float)v * kPhiUlp; }
+
+// Round to the nearest representable value, clamped to [kPhiMin, kPhiMax].
+__device__ __forceinline__ int32_t phi_from_float(float v) {
+    float s = fminf(fmaxf(v, kPhiMin), kPhiMax) * kPhiInvUlp;
+    return __float2int_rn(s);
+}
+
+// ---- lattice ---------------------------------------------------------------
+
+// D3Q27 weight of velocity (cx, cy, cz): 8/27, 2/27, 1/54, 1/216 by |c|^2.
+__host__ __device__ constexpr float w27(int cx, int cy, int cz) {
+    return (cx * cx + cy * cy + cz * cz) == 0   ? 8.0f / 27.0f
+           : (cx * cx + cy * cy + cz * cz) == 1 ? 2.0f / 27.0f
+           : (cx * cx + cy * cy + cz * cz) == 2 ? 1.0f / 54.0f
+                                                : 1.0f / 216.0f;
+}
+
+// Neighbour coordinate v = c + d with |d| <= 1 (or a clamped halo further out):
+// wrapped on a periodic axis, clamped to [0, n-1] otherwise.
+__device__ __forceinline__ int nb_coord(int v, int n, int periodic) {
+    if (periodic) return v < 0 ? v + n : (v >= n ? v - n : v);
+    return v < 0 ? 0 : (v >= n ? n - 1 : v);
+}
+
+__device__ __forceinline__ bool is_boundary_node(const Geo &g, int x, int y, int z) {
+    return (!g.per[0] && (x == 0 || x == g.nx - 1)) || (!g.per[1] && (y == 0 || y == g.ny - 1)) ||
+           (!g.per[2] && (z == 0 || z == g.nz - 1));
+}
+
+__device__ __forceinline__ long long node_id(const Geo &g, int x, int y, int z) {
+    return (long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z);
+}
+
+// ---- counter-based noise: SplitMix64 finaliser (Steele, Lea, Flood 2014) ----
+
+__host__ __device__ inline unsigned long long splitmix_finalise(unsigned long long z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+// xi in [-1, 1) from 24 random bits; counter = stream*2^62 + step*2^32 + node*4 + comp.
+__device__ __forceinline__ float noise_xi(unsigned long long key, unsigned long long stream,
+                                          unsigned long long step, unsigned long long node,
+                                          unsigned long long comp) {
+    unsigned long long ctr = (stream << 62) + (step << 32) + (node << 2) + comp;
+    unsigned long long h = splitmix_finalise(key ^ ctr);
+    return (float)(unsigned int)(h >> 40) * (1.0f / 8388608.0f) - 1.0f;
+}
+
+}  // namespace tslb

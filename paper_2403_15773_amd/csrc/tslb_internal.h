@@ -1,0 +1,76 @@
+// Host-side internals of the TSLB library: the context and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/tslb.h"
+#include "tslb_device.h"
+
+namespace tslb {
+
+// A view of one state buffer.
+struct StateView {
+    void *mom;      // ten planes of the storage type
+    int32_t *phi;   // phase-field plane (fixed point, 30 fractional bits)
+};
+
+// Scratch planes (binary32) used off the per-step path: host staging of
+// physical fields and the interface geometry of set/readout.
+struct Scratch {
+    float *stage = nullptr;  // 11 planes: rho - 1, u(3), P(6), phi
+    float *geo = nullptr;    // 9 planes: G(3), n(3), F(3)
+    double *partial = nullptr;      // per block: sum rho', finite probe
+    long long *partial_i = nullptr; // per block: sum of fixed-point phi
+    double *result = nullptr;       // sum rho', finite probe
+    long long *result_i = nullptr;  // sum of fixed-point phi
+    size_t partial_blocks = 0;
+};
+
+struct StepTimer {
+    bool enabled = false;
+    std::vector<hipEvent_t> ev;  // pairs (start, stop) per timed launch
+    size_t used = 0;             // pairs recorded in the last tslb_step
+};
+
+}  // namespace tslb
+
+struct tslb_ctx {
+    tslb_params p;
+    tslb::Geo geo;
+    tslb::Phys phys;
+    tslb::Scales scales;
+    int storage;
+    bool has_boundary;
+    size_t plane_bytes;   // bytes of one moment plane (storage type)
+    size_t buffer_bytes;  // bytes of one state buffer
+    void *base = nullptr; // both buffers
+    bool owns_base = false;
+    tslb::StateView buf[2];
+    int cur = 0;
+    int64_t step = 0;
+    bool state_set = false;
+    hipStream_t stream = nullptr;
+    bool owns_stream = false;
+    tslb::Scratch scratch;
+    tslb::StepTimer timer;
+    std::string err;
+};
+
+namespace tslb {
+
+size_t plane_elems(long long N);
+size_t state_buffer_bytes(long long N, int storage);
+
+// Launchers (all asynchronous on `s`); each returns the hipError_t of the launch.
+hipError_t launch_geometry(const tslb_ctx *c, const int32_t *phi, float *geo_planes, hipStream_t s);
+hipError_t launch_set_state(const tslb_ctx *c, const float *stage, float *geo_planes, StateView out, hipStream_t s);
+hipError_t launch_readout(const tslb_ctx *c, StateView in, const float *geo_planes, float *stage, hipStream_t s);
+hipError_t launch_boundary(const tslb_ctx *c, StateView st, int64_t step, hipStream_t s);
+hipError_t launch_step(const tslb_ctx *c, StateView in, StateView out, hipStream_t s);
+hipError_t launch_diagnostics(const tslb_ctx *c, StateView st, const Scratch &sc, hipStream_t s);
+size_t diagnostics_blocks(const tslb_ctx *c);
+
+}  // namespace tslb

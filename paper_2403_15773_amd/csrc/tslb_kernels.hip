@@ -1,0 +1,503 @@
+// Auxiliary kernels of the TSLB library (gfx950): interface geometry, the
+// physical <-> raw conversions of set-state and readout, the boundary-layer fill
+// and the conservation diagnostics; plus the per-destination gather step, a
+// direct transcription of the pull update used as the simple reference kernel.
+#include "tslb_internal.h"
+
+namespace tslb {
+
+constexpr int kBlock = 256;
+
+size_t plane_elems(long long N) { return (size_t)((N + 63) / 64 * 64); }
+
+size_t state_buffer_bytes(long long N, int storage) {
+    size_t ld = plane_elems(N);
+    size_t esz = storage == ST_FP32 ? 4 : 2;
+    size_t mom = ((size_t)kPlanes * ld * esz + 255) / 256 * 256;
+    return mom + ld * 4;
+}
+
+__device__ __forceinline__ void decompose(const Geo &g, long long id, int &x, int &y, int &z) {
+    x = (int)(id % g.nx);
+    long long r = id / g.nx;
+    y = (int)(r % g.ny);
+    z = (int)(r / g.ny);
+}
+
+template <int ST>
+__device__ __forceinline__ const typename Store<ST>::T *plane(const StateView &v, const Geo &g, int p) {
+    return (const typename Store<ST>::T *)v.mom + (long long)p * g.ld;
+}
+template <int ST>
+__device__ __forceinline__ typename Store<ST>::T *plane_w(const StateView &v, const Geo &g, int p) {
+    return (typename Store<ST>::T *)v.mom + (long long)p * g.ld;
+}
+
+// Load the ten raw moments of node id: m[0] = rho', m[1..3] = ubar, m[4..9] = Q.
+template <int ST>
+__device__ __forceinline__ void load_raw(const StateView &v, const Geo &g, const Scales &sc, long long id,
+                                         float m[10]) {
+    using S = Store<ST>;
+    m[0] = S::load(plane<ST>(v, g, 0), id, sc.s2);
+#pragma unroll
+    for (int p = 1; p < 4; ++p) m[p] = S::load(plane<ST>(v, g, p), id, sc.s1);
+#pragma unroll
+    for (int p = 4; p < 10; ++p) m[p] = S::load(plane<ST>(v, g, p), id, sc.s2);
+}
+
+template <int ST>
+__device__ __forceinline__ void store_raw(const StateView &v, const Geo &g, const Scales &sc, long long id,
+                                          const float m[10]) {
+    using S = Store<ST>;
+    S::store(plane_w<ST>(v, g, 0), id, m[0], sc.inv_s2);
+#pragma unroll
+    for (int p = 1; p < 4; ++p) S::store(plane_w<ST>(v, g, p), id, m[p], sc.inv_s1);
+#pragma unroll
+    for (int p = 4; p < 10; ++p) S::store(plane_w<ST>(v, g, p), id, m[p], sc.inv_s2);
+}
+
+// ---- interface geometry, materialised (set-state, readout, gather step) ----
+
+// G = (1/c_s^2) sum_i w_i c_i phi(y + c_i) (phi index clamped on walls) and
+// n = G/(|G| + eps): Eq. 21 with the isotropic D3Q27 stencil.  The sum runs
+// over the 13 pairs (c, -c) as exact fixed-point differences phi(y+c) - phi(y-c),
+// so a uniform field gives exactly G = 0 and phi near 1 loses no digits.
+__device__ __forceinline__ bool pair_lead(int cx, int cy, int cz) {
+    return cx > 0 || (cx == 0 && (cy > 0 || (cy == 0 && cz > 0)));
+}
+
+__global__ __launch_bounds__(kBlock) void k_gradient(Geo g, const int32_t *__restrict__ phi, float *__restrict__ geo,
+                                                     float eps) {
+    long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.N) return;
+    int x, y, z;
+    decompose(g, id, x, y, z);
+    float G0 = 0.f, G1 = 0.f, G2 = 0.f;
+#pragma unroll
+    for (int cz = -1; cz <= 1; ++cz)
+#pragma unroll
+        for (int cy = -1; cy <= 1; ++cy)
+#pragma unroll
+            for (int cx = -1; cx <= 1; ++cx) {
+                if (!pair_lead(cx, cy, cz)) continue;
+                int32_t a = phi[node_id(g, nb_coord(x + cx, g.nx, g.per[0]), nb_coord(y + cy, g.ny, g.per[1]),
+                                        nb_coord(z + cz, g.nz, g.per[2]))];
+                int32_t b = phi[node_id(g, nb_coord(x - cx, g.nx, g.per[0]), nb_coord(y - cy, g.ny, g.per[1]),
+                                        nb_coord(z - cz, g.nz, g.per[2]))];
+                float d = (float)(a - b) * kPhiUlp;
+                float w = 3.0f * w27(cx, cy, cz);
+                if (cx) G0 += (w * cx) * d;
+                if (cy) G1 += (w * cy) * d;
+                if (cz) G2 += (w * cz) * d;
+            }
+    float inv = 1.0f / (sqrtf(G0 * G0 + G1 * G1 + G2 * G2) + eps);
+    const long long ld = g.ld;
+    geo[id] = G0;
+    geo[ld + id] = G1;
+    geo[2 * ld + id] = G2;
+    geo[3 * ld + id] = G0 * inv;
+    geo[4 * ld + id] = G1 * inv;
+    geo[5 * ld + id] = G2 * inv;
+}
+
+// kappa = div n with the same stencil (pair differences); F = -sigma kappa G
+// (Eq. 20); F = 0 on boundary-layer nodes.
+__global__ __launch_bounds__(kBlock) void k_force(Geo g, float sigma, float *__restrict__ geo) {
+    long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.N) return;
+    int x, y, z;
+    decompose(g, id, x, y, z);
+    const long long ld = g.ld;
+    float k = 0.f;
+#pragma unroll
+    for (int cz = -1; cz <= 1; ++cz)
+#pragma unroll
+        for (int cy = -1; cy <= 1; ++cy)
+#pragma unroll
+            for (int cx = -1; cx <= 1; ++cx) {
+                if (!pair_lead(cx, cy, cz)) continue;
+                long long sa = node_id(g, nb_coord(x + cx, g.nx, g.per[0]), nb_coord(y + cy, g.ny, g.per[1]),
+                                       nb_coord(z + cz, g.nz, g.per[2]));
+                long long sb = node_id(g, nb_coord(x - cx, g.nx, g.per[0]), nb_coord(y - cy, g.ny, g.per[1]),
+                                       nb_coord(z - cz, g.nz, g.per[2]));
+                float w = 3.0f * w27(cx, cy, cz);
+                if (cx) k += (w * cx) * (geo[3 * ld + sa] - geo[3 * ld + sb]);
+                if (cy) k += (w * cy) * (geo[4 * ld + sa] - geo[4 * ld + sb]);
+                if (cz) k += (w * cz) * (geo[5 * ld + sa] - geo[5 * ld + sb]);
+            }
+    bool bnd = is_boundary_node(g, x, y, z);
+    float a = bnd ? 0.f : -sigma * k;
+    geo[6 * ld + id] = a * geo[id];
+    geo[7 * ld + id] = a * geo[ld + id];
+    geo[8 * ld + id] = a * geo[2 * ld + id];
+}
+
+// ---- physical <-> raw ----
+
+// stage planes: 0 rho - 1, 1..3 u, 4..9 P, 10 phi.
+// Raw: rho' = rho - 1, ubar = u - F/(2 rho), Q = P - F F/(4 rho); F comes from
+// the fixed-point phi already written into `out`.
+__global__ __launch_bounds__(kBlock) void k_stage_phi(Geo g, const float *__restrict__ stage, StateView out) {
+    long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.N) return;
+    out.phi[id] = phi_from_float(stage[10 * g.ld + id]);
+}
+
+template <int ST>
+__global__ __launch_bounds__(kBlock) void k_set_state(Geo g, Scales sc, const float *__restrict__ stage,
+                                                      const float *__restrict__ geo, StateView out) {
+    long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.N) return;
+    const long long ld = g.ld;
+    float drho = stage[id];
+    float inv = 1.0f / (1.0f + drho);
+    float F[3] = {geo[6 * ld + id], geo[7 * ld + id], geo[8 * ld + id]};
+    float m[10];
+    m[0] = drho;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) m[1 + a] = stage[(1 + a) * ld + id] - 0.5f * inv * F[a];
+    const int A[6] = {0, 1, 2, 0, 0, 1}, B[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int s = 0; s < 6; ++s) m[4 + s] = stage[(4 + s) * ld + id] - 0.25f * inv * F[A[s]] * F[B[s]];
+    store_raw<ST>(out, g, sc, id, m);
+}
+
+template <int ST>
+__global__ __launch_bounds__(kBlock) void k_readout(Geo g, Scales sc, StateView in, const float *__restrict__ geo,
+                                                    float *__restrict__ stage) {
+    long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.N) return;
+    const long long ld = g.ld;
+    float m[10];
+    load_raw<ST>(in, g, sc, id, m);
+    float inv = 1.0f / (1.0f + m[0]);
+    float F[3] = {geo[6 * ld + id], geo[7 * ld + id], geo[8 * ld + id]};
+    stage[id] = m[0];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) stage[(1 + a) * ld + id] = m[1 + a] + 0.5f * inv * F[a];
+    const int A[6] = {0, 1, 2, 0, 0, 1}, B[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int s = 0; s < 6; ++s) stage[(4 + s) * ld + id] = m[4 + s] + 0.25f * inv * F[A[s]] * F[B[s]];
+    stage[10 * ld + id] = phi_to_float(in.phi[id]);
+}
+
+// ---- boundary layers (Eqs. 9, 10) ----
+
+// One thread per node of a face (blockIdx.y = face -x,+x,-y,+y,-z,+z).  A node
+// on several faces belongs to the face of the highest axis (z, then y, then x).
+// It reads only interior nodes (its x_F, each coordinate clamped to [1, n-2])
+// and writes only itself, so the fill is race-free and idempotent.
+template <int ST>
+__global__ __launch_bounds__(kBlock) void k_boundary(Geo g, Phys ph, Scales sc, StateView st,
+                                                     unsigned long long step) {
+    const int face = blockIdx.y, axis = face >> 1, side = face & 1;
+    if (g.per[axis]) return;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)n[a1] * n[a2]) return;
+    int v[3];
+    v[axis] = side ? n[axis] - 1 : 0;
+    v[a1] = (int)(t % n[a1]);
+    v[a2] = (int)(t / n[a1]);
+    for (int b = axis + 1; b < 3; ++b)
+        if (!g.per[b] && (v[b] == 0 || v[b] == n[b] - 1)) return;
+    int f[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) f[b] = g.per[b] ? v[b] : min(max(v[b], 1), n[b] - 2);
+    long long idF = node_id(g, f[0], f[1], f[2]);
+    long long id = node_id(g, v[0], v[1], v[2]);
+    float m[10];
+    load_raw<ST>(st, g, sc, idF, m);
+    int32_t phi = st.phi[idF];
+    switch (ph.bc[face]) {
+    case TSLB_BC_FREESLIP:
+        m[1 + axis] = 0.f;
+        // Q components with exactly one index on the wall normal: xy, xz, yz = 7, 8, 9
+        if (axis == 0) { m[7] = 0.f; m[8] = 0.f; }
+        if (axis == 1) { m[7] = 0.f; m[9] = 0.f; }
+        if (axis == 2) { m[8] = 0.f; m[9] = 0.f; }
+        break;
+    case TSLB_BC_NOSLIP:
+        m[1] = m[2] = m[3] = 0.f;
+        break;
+    case TSLB_BC_OUTFLOW:
+        m[0] = 0.f;
+        break;
+    case TSLB_BC_INLET: {
+        float dx = v[0] - 0.5f * (g.nx - 1), dy = v[1] - 0.5f * (g.ny - 1);
+        float r = sqrtf(dx * dx + dy * dy);
+        float s = 0.5f * (1.0f - tanhf(2.0f * (r - 0.5f * ph.inlet_d) / ph.width));
+        float xi = noise_xi(ph.noise_key, 1ull, step, (unsigned long long)(v[0] + (long long)g.nx * v[1]), 2ull);
+        m[1] = 0.f;
+        m[2] = 0.f;
+        m[3] = ph.inlet_u * s * (1.0f + ph.inlet_noise * xi);
+        phi = phi_from_float(s);
+        break;
+    }
+    default:
+        break;
+    }
+    store_raw<ST>(st, g, sc, id, m);
+    st.phi[id] = phi;
+}
+
+// ---- diagnostics ----
+
+// Per-block partial sums: rho' (binary32 Kahan per thread, binary64 across the
+// block), phi (exact: int64 sum of the fixed-point values) and a finiteness
+// probe (sum of 0*v over the moments: NaN iff some value is not finite).
+template <int ST>
+__global__ __launch_bounds__(kBlock) void k_diag_partial(Geo g, Scales sc, StateView st, double *partial,
+                                                         long long *partial_i) {
+    __shared__ double red[2][kBlock];
+    __shared__ long long redi[kBlock];
+    float s0 = 0.f, c0 = 0.f, probe = 0.f;
+    long long sphi = 0;
+    for (long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x; id < g.N;
+         id += (long long)gridDim.x * blockDim.x) {
+        float m[10];
+        load_raw<ST>(st, g, sc, id, m);
+        float y0 = m[0] - c0, t0 = s0 + y0;
+        c0 = (t0 - s0) - y0;
+        s0 = t0;
+        sphi += st.phi[id];
+        float z = 0.f;
+#pragma unroll
+        for (int p = 0; p < 10; ++p) z += 0.f * m[p];
+        probe += z;
+    }
+    red[0][threadIdx.x] = (double)s0 - (double)c0;
+    red[1][threadIdx.x] = (double)probe;
+    redi[threadIdx.x] = sphi;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+            redi[threadIdx.x] += redi[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = red[0][0];
+        partial[2 * blockIdx.x + 1] = red[1][0];
+        partial_i[blockIdx.x] = redi[0];
+    }
+}
+
+// Single block: sum the partials in a fixed order (deterministic).
+__global__ __launch_bounds__(kBlock) void k_diag_final(const double *partial, const long long *partial_i, int nblocks,
+                                                       double *result, long long *result_i) {
+    __shared__ double red[2][kBlock];
+    __shared__ long long redi[kBlock];
+    double a0 = 0.0, a1 = 0.0;
+    long long ai = 0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+        a0 += partial[2 * b];
+        a1 += partial[2 * b + 1];
+        ai += partial_i[b];
+    }
+    red[0][threadIdx.x] = a0;
+    red[1][threadIdx.x] = a1;
+    redi[threadIdx.x] = ai;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+            redi[threadIdx.x] += redi[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        result[0] = red[0][0];
+        result[1] = red[1][0];
+        result_i[0] = redi[0];
+    }
+}
+
+// ---- the gather step (simple reference kernel) ----
+
+// One thread per interior destination x: for each velocity c_i, read the raw
+// moments of the source x - c_i, rebuild f_i^post there and add it into the
+// moments of x; likewise for the seven phase populations.
+// Hydrodynamics in deviation form: each incoming f_i - w_i enters the sums as
+// w_i (t_i - rho'(x)), where w_i t_i = f_i^post - w_i and rho'(x) is the
+// destination's own density deviation; the subtracted terms have zero first and
+// second moments, so only the density sum gets rho'(x) back.
+// Phase field in exact integer streaming: a source y sends base + a_k to +c_k,
+// base - a_k to -c_k and phi(y) - 6 base to itself, base = (phi + 4) >> 3 and
+// a_k = rint(2^30 (1/8) phi (4 c_k.u + gamma (1 - phi) c_k.n)) (Eqs. 23, 24).
+template <int ST>
+__global__ __launch_bounds__(kBlock) void k_step_gather(Geo g, Phys ph, Scales sc, StateView in,
+                                                        const float *__restrict__ geo, StateView out) {
+    long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.N) return;
+    int x, y, z;
+    decompose(g, id, x, y, z);
+    if (is_boundary_node(g, x, y, z)) return;
+    const long long ld = g.ld;
+    const float omega1 = 1.0f - ph.omega;
+    const float rp_x = Store<ST>::load(plane<ST>(in, g, 0), id, sc.s2);
+    float acc[10];
+#pragma unroll
+    for (int p = 0; p < 10; ++p) acc[p] = 0.f;
+    int32_t phin = 0;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+        const long long s = node_id(g, nb_coord(x - cx, g.nx, g.per[0]), nb_coord(y - cy, g.ny, g.per[1]),
+                                    nb_coord(z - cz, g.nz, g.per[2]));
+        float m[10];
+        load_raw<ST>(in, g, sc, s, m);
+        const float F0 = geo[6 * ld + s], F1 = geo[7 * ld + s], F2 = geo[8 * ld + s];
+        const float rho = 1.0f + m[0];
+        const float inv = 1.0f / rho;
+        const float u0 = m[1] + 0.5f * inv * F0, u1 = m[2] + 0.5f * inv * F1, u2 = m[3] + 0.5f * inv * F2;
+        const float q = 0.25f * inv;
+        const float Pxx = m[4] + q * F0 * F0, Pyy = m[5] + q * F1 * F1, Pzz = m[6] + q * F2 * F2;
+        const float Pxy = m[7] + q * F0 * F1, Pxz = m[8] + q * F0 * F2, Pyz = m[9] + q * F1 * F2;
+        const float cu = cx * u0 + cy * u1 + cz * u2;
+        const float cF = cx * F0 + cy * F1 + cz * F2;
+        const float uu = u0 * u0 + u1 * u1 + u2 * u2;
+        const float uF = u0 * F0 + u1 * F1 + u2 * F2;
+        const float cPc = cx * cx * Pxx + cy * cy * Pyy + cz * cz * Pzz +
+                          2.0f * (cx * cy * Pxy + cx * cz * Pxz + cy * cz * Pyz);
+        const float trP = Pxx + Pyy + Pzz;
+        const float cPu = cx * (Pxx * u0 + Pxy * u1 + Pxz * u2) + cy * (Pxy * u0 + Pyy * u1 + Pyz * u2) +
+                          cz * (Pxz * u0 + Pyz * u1 + Pzz * u2);
+        const float X = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu + 4.5f * cu * (cu * cu - uu);
+        const float Nq = 4.5f * cPc - 1.5f * trP + 13.5f * cu * cPc - 4.5f * cu * trP - 9.0f * cPu;
+        const float Sg = 1.5f * cF + 4.5f * cu * cF - 1.5f * uF;
+        const float t = m[0] + rho * X + omega1 * Nq + Sg;
+        const float df = w27(cx, cy, cz) * (t - rp_x);
+        acc[0] += df;
+        if (cx) acc[1] += cx * df;
+        if (cy) acc[2] += cy * df;
+        if (cz) acc[3] += cz * df;
+        acc[4] += (cx * cx - 1.0f / 3.0f) * df;
+        acc[5] += (cy * cy - 1.0f / 3.0f) * df;
+        acc[6] += (cz * cz - 1.0f / 3.0f) * df;
+        if (cx * cy) acc[7] += (cx * cy) * df;
+        if (cx * cz) acc[8] += (cx * cz) * df;
+        if (cy * cz) acc[9] += (cy * cz) * df;
+        if (cx * cx + cy * cy + cz * cz <= 1) {
+            const int32_t ps = in.phi[s];
+            const int32_t base = (ps + 4) >> 3;
+            if (cx | cy | cz) {
+                // a_k for the positive axis direction; the population along c = -e is base - a_e
+                const int ax = cx ? 0 : (cy ? 1 : 2);
+                const float sgn = (float)(cx + cy + cz);
+                const float ue = ax == 0 ? u0 : (ax == 1 ? u1 : u2);
+                const float ne = geo[(3 + ax) * ld + s];
+                const float phis = phi_to_float(ps);
+                const float omphi = (float)(kPhiOne - ps) * kPhiUlp;
+                const float h = 0.125f * phis * (4.0f * ue + ph.gamma * omphi * ne);
+                const int32_t a = __float2int_rn(h * kPhiInvUlp);
+                phin += base + (sgn > 0.f ? a : -a);
+            } else {
+                phin += ps - 6 * base;
+            }
+        }
+    }
+    const float drho = rp_x + acc[0];
+    const float inv = 1.0f / (1.0f + drho);
+    float m[10];
+    m[0] = drho;
+    m[1] = acc[1] * inv;
+    m[2] = acc[2] * inv;
+    m[3] = acc[3] * inv;
+    m[4] = acc[4] - acc[1] * acc[1] * inv;
+    m[5] = acc[5] - acc[2] * acc[2] * inv;
+    m[6] = acc[6] - acc[3] * acc[3] * inv;
+    m[7] = acc[7] - acc[1] * acc[2] * inv;
+    m[8] = acc[8] - acc[1] * acc[3] * inv;
+    m[9] = acc[9] - acc[2] * acc[3] * inv;
+    store_raw<ST>(out, g, sc, id, m);
+    out.phi[id] = phin;
+}
+
+// ---- launchers ----
+
+static unsigned grid_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+hipError_t launch_geometry(const tslb_ctx *c, const int32_t *phi, float *geo, hipStream_t s) {
+    hipLaunchKernelGGL(k_gradient, dim3(grid_for(c->geo.N)), dim3(kBlock), 0, s, c->geo, phi, geo, c->phys.eps);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_force, dim3(grid_for(c->geo.N)), dim3(kBlock), 0, s, c->geo, c->phys.sigma, geo);
+    return hipGetLastError();
+}
+
+#define TSLB_DISPATCH(ST_VAR, KERNEL, ...)                                          \
+    do {                                                                            \
+        switch (ST_VAR) {                                                           \
+        case ST_FP32: hipLaunchKernelGGL(KERNEL<ST_FP32>, __VA_ARGS__); break;      \
+        case ST_FP16: hipLaunchKernelGGL(KERNEL<ST_FP16>, __VA_ARGS__); break;      \
+        default: hipLaunchKernelGGL(KERNEL<ST_BF16>, __VA_ARGS__); break;           \
+        }                                                                           \
+    } while (0)
+
+hipError_t launch_set_state(const tslb_ctx *c, const float *stage, float *geo, StateView out, hipStream_t s) {
+    hipLaunchKernelGGL(k_stage_phi, dim3(grid_for(c->geo.N)), dim3(kBlock), 0, s, c->geo, stage, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_geometry(c, out.phi, geo, s);
+    if (e != hipSuccess) return e;
+    TSLB_DISPATCH(c->storage, k_set_state, dim3(grid_for(c->geo.N)), dim3(kBlock), 0, s, c->geo, c->scales, stage,
+                  geo, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_readout(const tslb_ctx *c, StateView in, const float *geo, float *stage, hipStream_t s) {
+    TSLB_DISPATCH(c->storage, k_readout, dim3(grid_for(c->geo.N)), dim3(kBlock), 0, s, c->geo, c->scales, in, geo,
+                  stage);
+    return hipGetLastError();
+}
+
+hipError_t launch_boundary(const tslb_ctx *c, StateView st, int64_t step, hipStream_t s) {
+    if (!c->has_boundary) return hipSuccess;
+    long long nx = c->geo.nx, ny = c->geo.ny, nz = c->geo.nz;
+    long long face_max = nx * ny;
+    if (ny * nz > face_max) face_max = ny * nz;
+    if (nx * nz > face_max) face_max = nx * nz;
+    TSLB_DISPATCH(c->storage, k_boundary, dim3(grid_for(face_max), 6), dim3(kBlock), 0, s, c->geo, c->phys,
+                  c->scales, st, (unsigned long long)step);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_gather(const tslb_ctx *c, StateView in, const float *geo, StateView out, hipStream_t s) {
+    TSLB_DISPATCH(c->storage, k_step_gather, dim3(grid_for(c->geo.N)), dim3(kBlock), 0, s, c->geo, c->phys,
+                  c->scales, in, geo, out);
+    return hipGetLastError();
+}
+
+size_t diagnostics_blocks(const tslb_ctx *c) {
+    long long b = grid_for(c->geo.N);
+    return (size_t)(b < 1024 ? b : 1024);
+}
+
+hipError_t launch_diagnostics(const tslb_ctx *c, StateView st, const Scratch &sc, hipStream_t s) {
+    TSLB_DISPATCH(c->storage, k_diag_partial, dim3((unsigned)sc.partial_blocks), dim3(kBlock), 0, s, c->geo,
+                  c->scales, st, sc.partial, sc.partial_i);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kBlock), 0, s, sc.partial, sc.partial_i, (int)sc.partial_blocks,
+                       sc.result, sc.result_i);
+    return hipGetLastError();
+}
+
+}  // namespace tslb
+
+namespace tslb {
+
+// One step from `in` to `out`: the materialised interface geometry of `in`,
+// then the gather update of every interior node.
+hipError_t launch_step(const tslb_ctx *c, StateView in, StateView out, hipStream_t s) {
+    hipError_t e = launch_geometry(c, in.phi, c->scratch.geo, s);
+    if (e != hipSuccess) return e;
+    return launch_step_gather(c, in, c->scratch.geo, out, s);
+}
+
+}  // namespace tslb

@@ -1,0 +1,227 @@
+"""Thin ctypes binding of ``libtslb.so`` (the C-ABI in ``include/tslb.h``).
+
+Argument marshalling only: every step of the method runs in the HIP kernels.
+The library must have been built (``__graft_entry__.build()``); there is no
+fallback, and a missing library raises.  PyTorch is optional: a torch CUDA
+tensor may be handed in as the device allocation and a torch stream as the
+stream, but nothing here computes with torch.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtslb.so")
+ABI_VERSION = 1
+
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSTABLE, E_STATE = 0, -1, -2, -3, -4, -5
+BC_PERIODIC, BC_FREESLIP, BC_INLET, BC_OUTFLOW, BC_NOSLIP = 0, 1, 2, 3, 4
+STORE_FP32, STORE_FP16, STORE_BF16 = 0, 1, 2
+STORAGE = {"fp32": STORE_FP32, "fp16": STORE_FP16, "bf16": STORE_BF16}
+
+EXPORTS = [
+    "tslb_params_init", "tslb_params_size", "tslb_required_bytes", "tslb_create", "tslb_set_state", "tslb_step", "tslb_sync",
+    "tslb_moments", "tslb_phase", "tslb_state_bytes", "tslb_get_state_raw", "tslb_set_state_raw",
+    "tslb_diagnostics", "tslb_step_index", "tslb_set_timing", "tslb_last_step_kernel_ms", "tslb_destroy",
+    "tslb_last_error",
+]
+
+
+class TslbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("tslb error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("bc", ctypes.c_int32 * 6),
+        ("nu", ctypes.c_double), ("sigma", ctypes.c_double), ("width", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("eps", ctypes.c_double),
+        ("inlet_u", ctypes.c_double), ("inlet_d", ctypes.c_double), ("inlet_noise", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("storage", ctypes.c_int32),
+        ("u_scale", ctypes.c_double),
+        ("check_interval", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("device_buffer", ctypes.c_void_p),
+        ("device_buffer_bytes", ctypes.c_size_t),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+_lock = threading.Lock()
+_lib = None
+_F = ctypes.POINTER(ctypes.c_float)
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the built library; raise if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise RuntimeError("libtslb.so is not built (expected at %s); run __graft_entry__.build()" % path)
+        lib = ctypes.CDLL(path)
+        vp, P = ctypes.c_void_p, ctypes.POINTER(Params)
+        sig = {
+            "tslb_params_init": (None, [P]),
+            "tslb_params_size": (ctypes.c_size_t, []),
+            "tslb_required_bytes": (ctypes.c_size_t, [P]),
+            "tslb_create": (ctypes.c_int, [P, ctypes.POINTER(vp)]),
+            "tslb_set_state": (ctypes.c_int, [vp, _F, _F, _F, _F, ctypes.c_int64]),
+            "tslb_step": (ctypes.c_int, [vp, ctypes.c_int64]),
+            "tslb_sync": (ctypes.c_int, [vp]),
+            "tslb_moments": (ctypes.c_int, [vp, _F, _F, _F]),
+            "tslb_phase": (ctypes.c_int, [vp, _F]),
+            "tslb_state_bytes": (ctypes.c_size_t, [vp]),
+            "tslb_get_state_raw": (ctypes.c_int, [vp, vp, ctypes.c_size_t]),
+            "tslb_set_state_raw": (ctypes.c_int, [vp, vp, ctypes.c_size_t, ctypes.c_int64]),
+            "tslb_diagnostics": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
+            "tslb_step_index": (ctypes.c_int64, [vp]),
+            "tslb_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
+            "tslb_last_step_kernel_ms": (ctypes.c_double, [vp]),
+            "tslb_destroy": (None, [vp]),
+            "tslb_last_error": (ctypes.c_char_p, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+        return lib
+
+
+def make_params(nx, ny, nz, nu, sigma=0.0, width=3.0, gamma=0.0, eps=-1.0, bc=(0,) * 6, inlet_u=0.0,
+                inlet_d=0.0, inlet_noise=0.0, seed=0, storage="fp32", u_scale=0.0, check_interval=0, device=0,
+                device_buffer=None, device_buffer_bytes=0, stream=None) -> Params:
+    lib = load_library()
+    p = Params()
+    lib.tslb_params_init(ctypes.byref(p))
+    p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+    for s in range(6):
+        p.bc[s] = int(bc[s])
+    p.nu, p.sigma, p.width, p.gamma, p.eps = float(nu), float(sigma), float(width), float(gamma), float(eps)
+    p.inlet_u, p.inlet_d, p.inlet_noise = float(inlet_u), float(inlet_d), float(inlet_noise)
+    p.seed = int(seed)
+    p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    p.u_scale = float(u_scale)
+    p.check_interval = int(check_interval)
+    p.device = int(device)
+    p.device_buffer = device_buffer
+    p.device_buffer_bytes = int(device_buffer_bytes)
+    p.stream = stream
+    return p
+
+
+def required_bytes(params: Params) -> int:
+    return load_library().tslb_required_bytes(ctypes.byref(params))
+
+
+def _f32(a, shape):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.shape != shape:
+        raise ValueError("expected shape %s, got %s" % (shape, a.shape))
+    return a
+
+
+class Simulation:
+    """One lattice on the GPU (a ``tslb_ctx``)."""
+
+    def __init__(self, params: Params | None = None, **kw):
+        self.lib = load_library()
+        self.params = params if params is not None else make_params(**kw)
+        h = ctypes.c_void_p()
+        rc = self.lib.tslb_create(ctypes.byref(self.params), ctypes.byref(h))
+        if rc != OK:
+            raise TslbError(rc, self.lib.tslb_last_error(None).decode())
+        self.h = h
+        self.shape = (self.params.nz, self.params.ny, self.params.nx)
+        self.N = self.params.nx * self.params.ny * self.params.nz
+
+    def _check(self, rc):
+        if rc != OK:
+            raise TslbError(rc, self.lib.tslb_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tslb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_state(self, rho_dev, u, P, phi, step=0):
+        """Physical fields: rho_dev = rho - 1, u (3,...), P (6,...), phi."""
+        sh = self.shape
+        rho_dev, u, P, phi = _f32(rho_dev, sh), _f32(u, (3,) + sh), _f32(P, (6,) + sh), _f32(phi, sh)
+        self._check(self.lib.tslb_set_state(self.h, rho_dev.ctypes.data_as(_F), u.ctypes.data_as(_F),
+                                            P.ctypes.data_as(_F), phi.ctypes.data_as(_F), int(step)))
+
+    def step(self, n=1):
+        self._check(self.lib.tslb_step(self.h, int(n)))
+
+    def sync(self):
+        self._check(self.lib.tslb_sync(self.h))
+
+    def moments(self):
+        """(rho - 1, u, P) at the current step, float32."""
+        sh = self.shape
+        drho, u, P = np.empty(sh, np.float32), np.empty((3,) + sh, np.float32), np.empty((6,) + sh, np.float32)
+        self._check(self.lib.tslb_moments(self.h, drho.ctypes.data_as(_F), u.ctypes.data_as(_F),
+                                          P.ctypes.data_as(_F)))
+        return drho, u, P
+
+    def phase(self):
+        phi = np.empty(self.shape, np.float32)
+        self._check(self.lib.tslb_phase(self.h, phi.ctypes.data_as(_F)))
+        return phi
+
+    def physical(self):
+        """dict with rho_dev (float32), rho = 1 + rho_dev (float64), u, P, phi."""
+        drho, u, P = self.moments()
+        return {"rho_dev": drho, "rho": 1.0 + drho.astype(np.float64), "u": u, "P": P, "phi": self.phase()}
+
+    @property
+    def state_bytes(self):
+        return self.lib.tslb_state_bytes(self.h)
+
+    def get_state_raw(self) -> np.ndarray:
+        buf = np.empty(self.state_bytes, np.uint8)
+        self._check(self.lib.tslb_get_state_raw(self.h, buf.ctypes.data, buf.nbytes))
+        return buf
+
+    def set_state_raw(self, buf: np.ndarray, step: int):
+        buf = np.ascontiguousarray(buf, np.uint8)
+        self._check(self.lib.tslb_set_state_raw(self.h, buf.ctypes.data, buf.nbytes, int(step)))
+
+    def diagnostics(self):
+        m, p = ctypes.c_double(), ctypes.c_double()
+        s, f = ctypes.c_int64(), ctypes.c_int32()
+        self._check(self.lib.tslb_diagnostics(self.h, ctypes.byref(m), ctypes.byref(p), ctypes.byref(s),
+                                              ctypes.byref(f)))
+        return {"mass": m.value, "phase": p.value, "step": s.value, "finite": bool(f.value)}
+
+    @property
+    def step_index(self):
+        return self.lib.tslb_step_index(self.h)
+
+    def set_timing(self, enable=True):
+        self._check(self.lib.tslb_set_timing(self.h, 1 if enable else 0))
+
+    def last_step_kernel_ms(self):
+        return self.lib.tslb_last_step_kernel_ms(self.h)

@@ -1,0 +1,97 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/tslb.h declares, its parameter struct matches the binding, and the
+host-side validation and sizing work without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2403_15773_amd import tslb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(tslb_\w+)\s*\(", txt))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(tslb.LIB_PATH):
+        from paper_2403_15773_amd import build
+        build.build()
+    return tslb.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    declared = _declared()
+    assert len(declared) >= 18
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared <= set(tslb.EXPORTS)
+
+
+def test_params_struct_layout(lib):
+    assert lib.tslb_params_size() == ctypes.sizeof(tslb.Params)
+
+
+def test_defaults_and_required_bytes(lib):
+    p = tslb.Params()
+    lib.tslb_params_init(ctypes.byref(p))
+    assert p.abi_version == tslb.ABI_VERSION and (p.nx, p.ny, p.nz) == (32, 32, 32)
+    # FP32: ten moment planes + phi, two buffers, planes padded to 64 elements
+    assert lib.tslb_required_bytes(ctypes.byref(p)) == 2 * 11 * 4 * 32 ** 3
+    p.storage = tslb.STORE_FP16
+    assert lib.tslb_required_bytes(ctypes.byref(p)) == 2 * (10 * 2 + 4) * 32 ** 3
+    p.storage = tslb.STORE_FP32
+    p.nx = 33  # 33*32*32 = 33792 = 528 * 64: still aligned
+    assert lib.tslb_required_bytes(ctypes.byref(p)) == 2 * 11 * 4 * 33792
+    p.nx, p.ny, p.nz = 5, 3, 3  # 45 -> padded to 64
+    assert lib.tslb_required_bytes(ctypes.byref(p)) == 2 * (((10 * 4 * 64 + 255) // 256) * 256 + 4 * 64)
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nu", 0.0), ("nu", -1.0), ("width", 0.0), ("sigma", -1e-3), ("storage", 7), ("abi_version", 99),
+    ("nx", 0), ("check_interval", -1)])
+def test_invalid_parameters_rejected_on_host(lib, field, value):
+    p = tslb.Params()
+    lib.tslb_params_init(ctypes.byref(p))
+    setattr(p, field, value)
+    assert lib.tslb_required_bytes(ctypes.byref(p)) == 0
+    h = ctypes.c_void_p()
+    assert lib.tslb_create(ctypes.byref(p), ctypes.byref(h)) == tslb.E_INVAL
+    assert h.value is None
+    assert len(lib.tslb_last_error(None)) > 0
+
+
+@pytest.mark.parametrize("bc", [(1, 0, 0, 0, 0, 0), (2, 1, 0, 0, 0, 0), (0, 0, 0, 0, 1, 2), (9, 9, 0, 0, 0, 0)])
+def test_invalid_boundary_sets_rejected(lib, bc):
+    p = tslb.Params()
+    lib.tslb_params_init(ctypes.byref(p))
+    for s in range(6):
+        p.bc[s] = bc[s]
+    p.inlet_d = 4.0
+    assert lib.tslb_required_bytes(ctypes.byref(p)) == 0
+
+
+def test_thin_axis_with_walls_rejected(lib):
+    p = tslb.Params()
+    lib.tslb_params_init(ctypes.byref(p))
+    p.nx = 3
+    p.bc[0] = p.bc[1] = tslb.BC_FREESLIP
+    assert lib.tslb_required_bytes(ctypes.byref(p)) == 0
+
+
+def test_null_context_calls_fail_cleanly(lib):
+    assert lib.tslb_step(None, 1) == tslb.E_INVAL
+    assert lib.tslb_sync(None) == tslb.E_INVAL
+    assert lib.tslb_step_index(None) == -1
+    assert lib.tslb_state_bytes(None) == 0
+    lib.tslb_destroy(None)

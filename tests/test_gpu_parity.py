@@ -1,0 +1,193 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle.
+
+Both sides start from the same float32-rounded physical fields.  The metric is
+the per-field relative L-infinity error max|X_gpu - X_oracle| / max|X_oracle|
+for X in rho - 1, u_a, P_ab and phi; the bar for binary32 storage is 1e-5.
+"""
+import numpy as np
+import pytest
+
+from paper_2403_15773_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+EPS = 1e-4  # regulariser of |grad phi|, passed explicitly to both sides
+TOL_FP32 = 1e-5
+P_NAMES = ["xx", "yy", "zz", "xy", "xz", "yz"]
+
+
+def _say(msg):
+    print("[gpu-test] " + msg, flush=True)
+
+
+def _f32(st):
+    """GPU inputs: float32 physical fields with rho replaced by rho_dev = rho - 1."""
+    out = {k: np.asarray(v, np.float32) for k, v in st.items() if k != "rho"}
+    out["rho_dev"] = np.asarray(np.asarray(st["rho"], np.float64) - 1.0, np.float32)
+    return out
+
+
+def _oracle_inputs(st32):
+    """The same fields in float64 for the oracle (rho = 1 + rho_dev)."""
+    out = {k: v.astype(np.float64) for k, v in st32.items() if k != "rho_dev"}
+    out["rho"] = 1.0 + st32["rho_dev"].astype(np.float64)
+    return out
+
+
+def field_errors(g, r):
+    """Per-field relative L-infinity errors (dict name -> (err, scale))."""
+    out = {}
+    pairs = [("rho-1", g["rho_dev"], r["rho"] - 1.0), ("phi", g["phi"], r["phi"])]
+    pairs += [("u" + "xyz"[a], g["u"][a], r["u"][a]) for a in range(3)]
+    pairs += [("P" + P_NAMES[s], g["P"][s], r["P"][s]) for s in range(6)]
+    for name, a, b in pairs:
+        a = np.asarray(a, np.float64)
+        scale = np.abs(b).max()
+        out[name] = (np.abs(a - b).max() / scale if scale > 0 else np.abs(a - b).max(), scale)
+    return out
+
+
+def run_both(p, state, steps, step0=0, storage="fp32", eps=EPS):
+    from oracle import Oracle
+    from paper_2403_15773_amd.tslb import Simulation
+    st = _f32(state)
+    kw = {k: v for k, v in p.items()}
+    sim = Simulation(**kw, eps=eps, storage=storage)
+    sim.set_state(**st, step=step0)
+    sim.step(steps)
+    g = sim.physical()
+    sim.close()
+    o = Oracle(p["nx"], p["ny"], p["nz"], nu=p["nu"], sigma=p["sigma"], width=p["width"], eps=eps,
+               bc=p["bc"], inlet_u=p.get("inlet_u", 0.0), inlet_d=p.get("inlet_d", 0.0),
+               inlet_noise=p.get("inlet_noise", 0.0), seed=p.get("seed", 0))
+    o.set_physical(**_oracle_inputs(st), step=step0)
+    o.step(steps)
+    r = o.physical()
+    o.close()
+    return g, r
+
+
+def assert_parity(g, r, tol, label):
+    errs = field_errors(g, r)
+    _say(label + " " + " ".join("%s=%.2e" % (k, v[0]) for k, v in errs.items()))
+    bad = {k: v for k, v in errs.items() if not v[0] <= tol}
+    assert not bad, "%s: fields above %.1e: %s" % (label, tol, bad)
+
+
+def test_droplet_32_parity_200_steps():
+    """The 32^3 periodic droplet (R = 8, W = 3, nu = 0.01, sigma = 0.01, noise 1e-3), 200 steps."""
+    _say("droplet32 fp32 200 steps")
+    p = inputs.droplet_params(32)
+    g, r = run_both(p, inputs.droplet(32, 8.0, 3.0, noise_amp=1e-3, seed=1), 200)
+    assert_parity(g, r, TOL_FP32, "droplet32")
+
+
+def test_ragged_periodic_box_parity():
+    """Non-cubic box whose sizes are not multiples of any tile (20 x 12 x 9)."""
+    _say("ragged 20x12x9 fp32 60 steps")
+    nx, ny, nz = 20, 12, 9
+    x, y, z = inputs.grid_coords(nx, ny, nz)
+    st = inputs.quiescent(nx, ny, nz)
+    r2 = (x - 9.3) ** 2 + (y - 5.1) ** 2 + (z - 4.2) ** 2
+    st["phi"] = 0.5 * (1 - np.tanh(2 * (np.sqrt(r2) - 3.5) / 2.5))
+    node = np.arange(nx * ny * nz, dtype=np.uint64)
+    st["u"] = 0.01 * np.stack([inputs.noise(3, 0, 0, node, a).reshape(nz, ny, nx) for a in range(3)])
+    p = dict(nx=nx, ny=ny, nz=nz, nu=0.02, sigma=0.02, width=2.5, bc=(0,) * 6)
+    g, r = run_both(p, st, 60)
+    assert_parity(g, r, TOL_FP32, "ragged")
+
+
+def test_mini_jet_parity():
+    """24 x 24 x 40 round jet (D = 8, U = 0.05, Re = 400, We = 40): inlet, outflow and
+    free-slip boundary layers, 200 steps."""
+    _say("mini-jet 24x24x40 fp32 200 steps")
+    p = inputs.jet_params(24, 24, 40, d=8.0, u=0.05, re=400.0, we=40.0, seed=9)
+    g, r = run_both(p, inputs.quiescent(24, 24, 40), 200, step0=5)
+    assert_parity(g, r, TOL_FP32, "mini-jet")
+
+
+def test_rest_state_is_bitwise_steady():
+    from paper_2403_15773_amd.tslb import Simulation
+    _say("rest state 16^3")
+    sim = Simulation(nx=16, ny=16, nz=16, nu=0.05, sigma=0.01, eps=EPS)
+    st = _f32(inputs.quiescent(16, 16, 16, phi=0.25))
+    sim.set_state(**st)
+    before = sim.get_state_raw()
+    sim.step(20)
+    after = sim.get_state_raw()
+    assert np.array_equal(before, after)
+
+
+def test_uniform_flow_is_steady():
+    from paper_2403_15773_amd.tslb import Simulation
+    _say("uniform flow 12x10x8")
+    sim = Simulation(nx=12, ny=10, nz=8, nu=0.05, sigma=0.01, eps=EPS)
+    st = inputs.quiescent(12, 10, 8, phi=0.4)
+    u0 = np.array([0.03, -0.02, 0.01])
+    st["u"][:] = u0[:, None, None, None]
+    sim.set_state(**_f32(st))
+    sim.step(20)
+    g = sim.physical()
+    assert np.abs(g["u"] - u0[:, None, None, None].astype(np.float32)).max() < 1e-7
+    assert np.abs(g["rho_dev"]).max() < 1e-6 and np.abs(g["P"]).max() < 1e-8
+    assert np.abs(g["phi"] - np.float32(0.4)).max() < 1e-7
+
+
+def test_conservation_diagnostics():
+    from paper_2403_15773_amd.tslb import Simulation
+    _say("conservation droplet32 200 steps")
+    p = inputs.droplet_params(32)
+    sim = Simulation(**p, eps=EPS)
+    st = _f32(inputs.droplet(32, 8.0, 3.0, noise_amp=1e-3, seed=1))
+    sim.set_state(**st)
+    d0 = sim.diagnostics()
+    sim.step(200)
+    d1 = sim.diagnostics()
+    assert d0["finite"] and d1["finite"] and d1["step"] == 200
+    assert abs(d0["mass"] - (1.0 + st["rho_dev"].astype(np.float64)).sum()) < 1e-6
+    assert abs(d1["mass"] - d0["mass"]) / d0["mass"] < 1e-9
+    assert d1["phase"] == d0["phase"]  # integer phase streaming conserves the sum exactly
+
+
+def test_checkpoint_resume_is_bitwise():
+    from paper_2403_15773_amd.tslb import Simulation
+    _say("checkpoint/resume mini-jet")
+    p = inputs.jet_params(16, 16, 24, d=6.0, u=0.05, re=300.0, we=50.0, seed=5)
+    st = _f32(inputs.quiescent(16, 16, 24))
+    a = Simulation(**p, eps=EPS)
+    a.set_state(**st)
+    a.step(60)
+    ck = a.get_state_raw()
+    a.step(40)
+    end_a = a.get_state_raw()
+    b = Simulation(**p, eps=EPS)
+    b.set_state_raw(ck, step=60)
+    b.step(40)
+    assert np.array_equal(end_a, b.get_state_raw())
+
+
+def test_runs_are_deterministic():
+    from paper_2403_15773_amd.tslb import Simulation
+    _say("determinism droplet 24^3")
+    st = _f32(inputs.droplet(24, 6.0, 3.0, noise_amp=1e-3, seed=4))
+    outs = []
+    for _ in range(2):
+        s = Simulation(nx=24, ny=24, nz=24, nu=0.01, sigma=0.01, eps=EPS)
+        s.set_state(**st)
+        s.step(50)
+        outs.append(s.get_state_raw())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_non_finite_state_is_reported():
+    from paper_2403_15773_amd.tslb import Simulation, TslbError, E_UNSTABLE
+    _say("non-finite detection")
+    st = inputs.quiescent(8, 8, 8, phi=0.5)
+    st["u"][0, 3, 3, 3] = np.nan
+    s = Simulation(nx=8, ny=8, nz=8, nu=0.05, sigma=0.0, eps=EPS, check_interval=2)
+    s.set_state(**_f32(st))
+    with pytest.raises(TslbError) as ei:
+        s.step(6)
+    assert ei.value.code == E_UNSTABLE
+    assert s.step_index == 2
+    assert not s.diagnostics()["finite"]
