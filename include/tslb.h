@@ -68,6 +68,13 @@ enum {
     TSLB_STORE_BF16 = 2
 };
 
+/* Step kernels (tslb_set_kernel). */
+enum {
+    TSLB_KERNEL_FUSED = 0,  /* one fused kernel per step (default) */
+    TSLB_KERNEL_GATHER = 1  /* simple reference: materialised geometry, then one
+                               thread per node gathering its 27 sources */
+};
+
 typedef struct tslb_ctx tslb_ctx;
 
 typedef struct tslb_params {
@@ -151,6 +158,11 @@ int tslb_set_timing(tslb_ctx *ctx, int enable);
  * last tslb_step() call made with timing enabled; synchronises.  Returns 0 if
  * no timed launch exists. */
 double tslb_last_step_kernel_ms(tslb_ctx *ctx);
+
+/* Select the step kernel (TSLB_KERNEL_*) and, for the fused kernel, the number
+ * of z planes a workgroup marches through (chunk_z >= 1; 0 keeps the current
+ * value).  Both kernels compute the same step up to rounding. */
+int tslb_set_kernel(tslb_ctx *ctx, int kernel, int chunk_z);
 
 /* Release the context and everything it allocated. */
 void tslb_destroy(tslb_ctx *ctx);

@@ -236,7 +236,7 @@ int tslb_step(tslb_ctx *c, int64_t nsteps) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
     if (nsteps < 0) return fail(c, TSLB_E_INVAL, "nsteps must be >= 0");
     if (!c->state_set) return fail(c, TSLB_E_STATE, "no state: call tslb_set_state first");
-    int rc = ensure_planes(c);
+    int rc = c->kernel == TSLB_KERNEL_GATHER ? ensure_planes(c) : TSLB_OK;
     if (rc) return rc;
     StepTimer &tm = c->timer;
     const size_t max_timed = 8192;
@@ -360,6 +360,15 @@ int tslb_diagnostics(tslb_ctx *c, double *mass, double *phase_sum, int64_t *step
 }
 
 int64_t tslb_step_index(const tslb_ctx *c) { return c ? c->step : -1; }
+
+int tslb_set_kernel(tslb_ctx *c, int kernel, int chunk_z) {
+    if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    if (kernel != TSLB_KERNEL_FUSED && kernel != TSLB_KERNEL_GATHER) return fail(c, TSLB_E_INVAL, "unknown kernel");
+    if (chunk_z < 0) return fail(c, TSLB_E_INVAL, "chunk_z must be >= 0");
+    c->kernel = kernel;
+    if (chunk_z > 0) c->chunk_z = chunk_z;
+    return TSLB_OK;
+}
 
 int tslb_set_timing(tslb_ctx *c, int enable) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");

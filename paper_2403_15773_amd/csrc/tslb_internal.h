@@ -56,6 +56,8 @@ struct tslb_ctx {
     bool owns_stream = false;
     tslb::Scratch scratch;
     tslb::StepTimer timer;
+    int kernel = TSLB_KERNEL_FUSED;  // step kernel selected by tslb_set_kernel
+    int chunk_z = 32;                // z planes per workgroup of the fused kernel
     std::string err;
 };
 
@@ -70,6 +72,7 @@ hipError_t launch_set_state(const tslb_ctx *c, const float *stage, float *geo_pl
 hipError_t launch_readout(const tslb_ctx *c, StateView in, const float *geo_planes, float *stage, hipStream_t s);
 hipError_t launch_boundary(const tslb_ctx *c, StateView st, int64_t step, hipStream_t s);
 hipError_t launch_step(const tslb_ctx *c, StateView in, StateView out, hipStream_t s);
+hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int lz, hipStream_t s);
 hipError_t launch_diagnostics(const tslb_ctx *c, StateView st, const Scratch &sc, hipStream_t s);
 size_t diagnostics_blocks(const tslb_ctx *c);
 

@@ -492,9 +492,10 @@ hipError_t launch_diagnostics(const tslb_ctx *c, StateView st, const Scratch &sc
 
 namespace tslb {
 
-// One step from `in` to `out`: the materialised interface geometry of `in`,
-// then the gather update of every interior node.
+// One step from `in` to `out`: the fused kernel, or (TSLB_KERNEL_GATHER) the
+// materialised interface geometry of `in` followed by the gather update.
 hipError_t launch_step(const tslb_ctx *c, StateView in, StateView out, hipStream_t s) {
+    if (c->kernel == TSLB_KERNEL_FUSED) return launch_step_fused(c, in, out, c->chunk_z, s);
     hipError_t e = launch_geometry(c, in.phi, c->scratch.geo, s);
     if (e != hipSuccess) return e;
     return launch_step_gather(c, in, c->scratch.geo, out, s);

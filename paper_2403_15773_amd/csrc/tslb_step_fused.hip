@@ -1,0 +1,507 @@
+// Fused thread-safe LB step for gfx950: one kernel reads the raw moments and
+// phase field of step t once from HBM and writes those of step t+1 once.
+//
+// Work decomposition.  A workgroup owns a 32 x 16 tile of (x, y) destination
+// columns and marches through a chunk of z planes.  Its 640 threads are
+//   t <  512 : destination column (t % 32, t / 32), also the source of that column,
+//   t <  612 : one of the 100 columns of the one-node halo ring (sources only),
+//   t >= 612 : idle in the source stages.
+// For every z plane the workgroup
+//   S1  stages the fixed-point phase field of plane p (3-node halo) in LDS,
+//   S2  computes G = grad(phi) and n = G/(|G| + eps) of plane p-1 (2-node halo),
+//   S3  computes kappa = div n and F = -sigma kappa G of plane p-2 (1-node halo),
+//   S4  rebuilds at every source of plane p-2 the 27 post-collision populations
+//       (as brackets t_i = f_i/w_i - 1) and the 7 phase populations,
+//   S5  moves them: x and y through LDS, z through registers (the populations of
+//       velocity c_z = -1, 0, +1 belong to destination planes p-3, p-2, p-1),
+//   S6  finishes destination plane p-3 and stores it.
+// Each destination node is written by exactly one thread and every read is of
+// step t, so the update is race-free (the thread-safe property of the method).
+//
+// Arithmetic (Eqs. 5-8, 15-19 with Guo forcing; Eqs. 20-24):
+//   source:  u = ubar + F/(2 rho), P = Q + F F/(4 rho), J = rho u + F/2,
+//            a2 = rho u u + (1-omega) P + (u F + F u)/2,
+//            a3_aab = rho u_a^2 u_b + (1-omega)(2 u_a P_ab + u_b P_aa),
+//            a3_xyz = rho u_x u_y u_z + (1-omega)(u_x P_yz + u_y P_xz + u_z P_xy),
+//            t(c) = rho' + 3 c.J + 4.5 H2(c):a2 + 4.5 H3(c):a3, evaluated on the
+//            27 velocities as a tensor product of 1-D quadratics in c_x, c_y, c_z;
+//   destination: moments sum_i w_i H(c_i) t_i(x - c_i) as a tensor product of
+//            1-D three-point transforms written relative to the middle value, so
+//            the large isotropic part cancels before rounding.
+// Precision: the source builds tau = t - rho' (no density part) and publishes its
+// rho' once; the destination forms t_i - rho'(own column, same plane) as
+// tau_i + (rho'(source) - rho'(own column)), exact differences of neighbours, and
+// puts rho'(own column) back into the zeroth moment only.  No sum is rounded at
+// the magnitude of rho' except the final density itself.
+#include "tslb_internal.h"
+
+namespace tslb {
+namespace fused {
+
+constexpr int TX = 32, TY = 16;
+constexpr int SX = TX + 2, SY = TY + 2, NSRC = SX * SY;   // sources: 34 x 18
+constexpr int GX = TX + 4, GY = TY + 4, NGEO = GX * GY;   // geometry: 36 x 20
+constexpr int PX = TX + 6, PY = TY + 6, NPHI = PX * PY;   // phase field: 38 x 22
+constexpr int NDST = TX * TY;                              // 512
+constexpr int NT = 640;                                    // threads per workgroup
+constexpr int NXCH = 29;                                   // exchange slots per source
+
+static_assert(NSRC <= NT && NDST <= NSRC, "tile does not fit the workgroup");
+static_assert(NPHI <= 2 * NT && NGEO <= 2 * NT, "staging loops assume two items per thread");
+
+struct Smem {
+    int32_t phi[4][NPHI];      // fixed-point phase field, ring of 4 planes
+    float n[3][3][NGEO];       // unit normal, ring of 3 planes
+    float G[2][3][NSRC];       // gradient on the source region, ring of 2 planes
+    float xch[NXCH][NSRC];     // populations crossing columns
+};
+
+// 1-D three-point transform of (a_-, a_0, a_+) with weights (1/6, 2/3, 1/6):
+// m0 = sum w a, m1 = sum w c a, m2 = sum w (c^2 - 1/3) a, written relative to a_0.
+struct Tr3 {
+    float m0, m1, m2;
+};
+__device__ __forceinline__ Tr3 tr3(float am, float a0, float ap) {
+    const float dm = am - a0, dp = ap - a0;
+    const float s = dm + dp;
+    Tr3 r;
+    r.m0 = fmaf(s, 1.0f / 6.0f, a0);
+    r.m1 = (dp - dm) * (1.0f / 6.0f);
+    r.m2 = s * (1.0f / 9.0f);
+    return r;
+}
+__device__ __forceinline__ float tr3_m0(float am, float a0, float ap) {
+    return fmaf((am - a0) + (ap - a0), 1.0f / 6.0f, a0);
+}
+
+// Quadratic A + B c + C (c^2 - 1/3) at c = -1, 0, +1.
+__device__ __forceinline__ void quad3(float A, float B, float C, float &vm, float &v0, float &vp) {
+    const float m = fmaf(C, 2.0f / 3.0f, A);
+    v0 = fmaf(C, -1.0f / 3.0f, A);
+    vm = m - B;
+    vp = m + B;
+}
+
+// Slot of direction (cx, cy) != (0, 0) in the exchange buffer of one z group.
+__device__ __forceinline__ constexpr int xy_slot(int cx, int cy) {
+    return ((cx + 1) + 3 * (cy + 1)) < 4 ? ((cx + 1) + 3 * (cy + 1)) : ((cx + 1) + 3 * (cy + 1)) - 1;
+}
+
+__device__ __forceinline__ int wrap_or_clamp(int v, int n, int periodic) {
+    if (periodic) {
+        v %= n;
+        return v < 0 ? v + n : v;
+    }
+    return v < 0 ? 0 : (v >= n ? n - 1 : v);
+}
+
+// The six 2-D moments X_pq = sum_{cx,cy} w(cx) w(cy) h_p(cx) h_q(cy) t(cx, cy) of
+// one z group, p, q in {00, 10, 01, 20, 02, 11} (order of the output array).
+__device__ __forceinline__ void xy_moments(const float t[9], float X[6]) {
+    // y stage, per c_x: t[(cx+1) + 3(cy+1)]
+    Tr3 y0 = tr3(t[0], t[3], t[6]);   // c_x = -1
+    Tr3 y1 = tr3(t[1], t[4], t[7]);   // c_x = 0
+    Tr3 y2 = tr3(t[2], t[5], t[8]);   // c_x = +1
+    Tr3 a = tr3(y0.m0, y1.m0, y2.m0);
+    X[0] = a.m0;                       // 00
+    X[1] = a.m1;                       // 10
+    X[3] = a.m2;                       // 20
+    Tr3 b = tr3(y0.m1, y1.m1, y2.m1);
+    X[2] = b.m0;                       // 01
+    X[5] = b.m1;                       // 11
+    X[4] = tr3_m0(y0.m2, y1.m2, y2.m2);  // 02
+}
+
+template <int ST>
+__global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, StateView in, StateView out, int lz,
+                                                   int tiles_x, int tiles_y) {
+    __shared__ Smem sm;
+    using S = Store<ST>;
+    using T = typename S::T;
+
+    // ---- tile and chunk of this workgroup ----
+    const int b = blockIdx.x;
+    const int tile = b % (tiles_x * tiles_y);
+    const int chunk = b / (tiles_x * tiles_y);
+    const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
+    const int z0 = chunk * lz;
+    const int z1 = min(z0 + lz, g.nz);  // destination planes [z0, z1)
+    const int t = threadIdx.x;
+    const long long plane = (long long)g.nx * g.ny;
+
+    // ---- this thread's source column (local sx, sy in the 34 x 18 region) ----
+    int sx = 0, sy = 0;
+    const bool is_dst = t < NDST;
+    const bool is_src = t < NSRC;
+    if (is_dst) {
+        sx = t % TX + 1;
+        sy = t / TX + 1;
+    } else if (is_src) {
+        const int r = t - NDST;
+        if (r < SX) { sx = r; sy = 0; }
+        else if (r < 2 * SX) { sx = r - SX; sy = SY - 1; }
+        else if (r < 2 * SX + TY) { sx = 0; sy = r - 2 * SX + 1; }
+        else { sx = SX - 1; sy = r - 2 * SX - TY + 1; }
+    }
+    const int sidx = sy * SX + sx;
+    const int gxs = x0 + sx - 1, gys = y0 + sy - 1;          // unwrapped global source column
+    const int cxs = wrap_or_clamp(gxs, g.nx, g.per[0]);
+    const int cys = wrap_or_clamp(gys, g.ny, g.per[1]);
+    const long long col_src = (long long)cxs + (long long)g.nx * cys;
+    const bool src_bnd_xy = (!g.per[0] && (gxs <= 0 || gxs >= g.nx - 1)) ||
+                            (!g.per[1] && (gys <= 0 || gys >= g.ny - 1));
+    // destination validity in x, y (interior of the lattice, inside the domain)
+    const bool dst_xy = is_dst && gxs < g.nx && gys < g.ny && !src_bnd_xy;
+
+    // ---- staging columns of the phase field (<= 2 per thread) ----
+    long long col_phi[2];
+    int phi_item[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int i = t + k * NT;
+        phi_item[k] = i < NPHI ? i : -1;
+        const int px = i % PX, py = i / PX;
+        const int gx = wrap_or_clamp(x0 - 3 + px, g.nx, g.per[0]);
+        const int gy = wrap_or_clamp(y0 - 3 + py, g.ny, g.per[1]);
+        col_phi[k] = (long long)gx + (long long)g.nx * gy;
+    }
+    // geometry items (<= 2 per thread): centre (gx, gy) in the 36 x 20 region
+    int geo_item[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int i = t + k * NT;
+        geo_item[k] = i < NGEO ? i : -1;
+    }
+
+    const float omega1 = 1.0f - ph.omega;
+    const float sigma = ph.sigma, gamma = ph.gamma, eps = ph.eps;
+
+    // carried destination state (see the S5 comment)
+    float XA[6], XB[6], XC[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) XA[k] = XB[k] = XC[k] = 0.f;
+    int32_t PA = 0, PC = 0;
+
+    // prefetched raw moments of the next source plane (own column)
+    float mom[10];
+    int32_t phi_next[2] = {0, 0};
+
+    auto plane_of = [&](int z) { return wrap_or_clamp(z, g.nz, g.per[2]); };
+    auto load_moments = [&](int z, float m[10]) {
+        const long long id = col_src + plane * plane_of(z);
+        const T *base = (const T *)in.mom;
+        m[0] = S::load(base, id, sc.s2);
+#pragma unroll
+        for (int p = 1; p < 4; ++p) m[p] = S::load(base + p * g.ld, id, sc.s1);
+#pragma unroll
+        for (int p = 4; p < 10; ++p) m[p] = S::load(base + p * g.ld, id, sc.s2);
+    };
+    auto load_phi = [&](int z, int32_t v[2]) {
+        const long long zoff = plane * plane_of(z);
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            if (phi_item[k] >= 0) v[k] = in.phi[col_phi[k] + zoff];
+    };
+
+    const int nit = (z1 - z0) + 6;
+    // prologue: phase plane z0 - 3 staged before the loop
+    {
+        int32_t v[2] = {0, 0};
+        load_phi(z0 - 3, v);
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            if (phi_item[k] >= 0) sm.phi[0][phi_item[k]] = v[k];
+        load_phi(z0 - 2, phi_next);
+    }
+    __syncthreads();
+
+    for (int it = 0; it < nit; ++it) {
+        const int p = z0 - 3 + it;  // phase plane staged now (S1)
+        const int q = p - 1;        // plane of G and n (S2)
+        const int r = p - 2;        // source plane (S3, S4)
+
+        // ---- S1: stage phi(p + 1) for the next iteration (slot it+1 mod 4) ----
+        if (it + 1 < nit) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                if (phi_item[k] >= 0) sm.phi[(it + 1) & 3][phi_item[k]] = phi_next[k];
+        }
+        // ---- S2: G and n of plane q from phi planes q-1, q, q+1 ----
+        if (it >= 2) {
+            const int32_t *pm = sm.phi[(it - 2) & 3], *p0 = sm.phi[(it - 1) & 3], *pp = sm.phi[it & 3];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int i = geo_item[k];
+                if (i < 0) continue;
+                const int gxl = i % GX, gyl = i / GX;
+                const int c = (gyl + 1) * PX + (gxl + 1);  // centre in the phi region
+                float G0 = 0.f, G1 = 0.f, G2 = 0.f;
+#pragma unroll
+                for (int cz = -1; cz <= 1; ++cz)
+#pragma unroll
+                    for (int cy = -1; cy <= 1; ++cy)
+#pragma unroll
+                        for (int cx = -1; cx <= 1; ++cx) {
+                            const bool lead = cx > 0 || (cx == 0 && (cy > 0 || (cy == 0 && cz > 0)));
+                            if (!lead) continue;
+                            const int32_t *pa = cz > 0 ? pp : (cz < 0 ? pm : p0);
+                            const int32_t *pb = cz > 0 ? pm : (cz < 0 ? pp : p0);
+                            const int32_t a = pa[c + cy * PX + cx];
+                            const int32_t bb = pb[c - cy * PX - cx];
+                            const float d = (float)(a - bb);
+                            const float w = 3.0f * w27(cx, cy, cz) * kPhiUlp;
+                            if (cx) G0 = fmaf(w * cx, d, G0);
+                            if (cy) G1 = fmaf(w * cy, d, G1);
+                            if (cz) G2 = fmaf(w * cz, d, G2);
+                        }
+                const float inv = 1.0f / (sqrtf(G0 * G0 + G1 * G1 + G2 * G2) + eps);
+                float *n = &sm.n[(it - 2) % 3][0][0];
+                n[i] = G0 * inv;
+                n[NGEO + i] = G1 * inv;
+                n[2 * NGEO + i] = G2 * inv;
+                const int ssx = gxl - 1, ssy = gyl - 1;
+                if (ssx >= 0 && ssx < SX && ssy >= 0 && ssy < SY) {
+                    float *Gs = &sm.G[it & 1][0][0];
+                    const int si = ssy * SX + ssx;
+                    Gs[si] = G0;
+                    Gs[NSRC + si] = G1;
+                    Gs[2 * NSRC + si] = G2;
+                }
+            }
+        }
+        // prefetch: phi plane p + 2 (staged next iteration), moments of plane r + 1
+        if (it + 2 < nit) load_phi(p + 2, phi_next);
+        float mom_cur[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) mom_cur[k] = mom[k];
+        if (is_src && it >= 3) load_moments(r + 1, mom);
+        __syncthreads();
+
+        if (it >= 4) {
+            // ---- S3: kappa and F at the source (plane r) ----
+            float F0 = 0.f, F1 = 0.f, F2 = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
+            int32_t phis = 0;
+            if (is_src) {
+                const float *nm = &sm.n[(it - 4) % 3][0][0], *n0p = &sm.n[(it - 3) % 3][0][0],
+                            *npp = &sm.n[(it - 2) % 3][0][0];
+                const int c = (sy + 1) * GX + (sx + 1);  // centre in the geometry region
+                float kap = 0.f;
+#pragma unroll
+                for (int cz = -1; cz <= 1; ++cz)
+#pragma unroll
+                    for (int cy = -1; cy <= 1; ++cy)
+#pragma unroll
+                        for (int cx = -1; cx <= 1; ++cx) {
+                            const bool lead = cx > 0 || (cx == 0 && (cy > 0 || (cy == 0 && cz > 0)));
+                            if (!lead) continue;
+                            const float *na = cz > 0 ? npp : (cz < 0 ? nm : n0p);
+                            const float *nb = cz > 0 ? nm : (cz < 0 ? npp : n0p);
+                            const int ia = c + cy * GX + cx, ib = c - cy * GX - cx;
+                            const float w = 3.0f * w27(cx, cy, cz);
+                            if (cx) kap = fmaf(w * cx, na[ia] - nb[ib], kap);
+                            if (cy) kap = fmaf(w * cy, na[NGEO + ia] - nb[NGEO + ib], kap);
+                            if (cz) kap = fmaf(w * cz, na[2 * NGEO + ia] - nb[2 * NGEO + ib], kap);
+                        }
+                const int zr = r;
+                const bool bnd = src_bnd_xy || (!g.per[2] && (zr <= 0 || zr >= g.nz - 1));
+                const float a = bnd ? 0.f : -sigma * kap;
+                const float *Gs = &sm.G[(it - 1) & 1][0][0];
+                F0 = a * Gs[sidx];
+                F1 = a * Gs[NSRC + sidx];
+                F2 = a * Gs[2 * NSRC + sidx];
+                n0 = n0p[c];
+                n1 = n0p[NGEO + c];
+                n2 = n0p[2 * NGEO + c];
+                phis = sm.phi[(it - 2) & 3][(sy + 2) * PX + (sx + 2)];
+            }
+
+            // ---- S4: post-collision populations of the source ----
+            float tm[9], t0[9], tp[9];  // groups c_z = -1, 0, +1, index (cx+1) + 3(cy+1)
+            int32_t base = 0, ax = 0, ay = 0, az = 0;
+            if (is_src) {
+                const float rp = mom_cur[0];
+                const float rho = 1.0f + rp;
+                const float inv = 1.0f / rho;
+                const float hF = 0.5f * inv, qF = 0.25f * inv;
+                const float u0 = fmaf(hF, F0, mom_cur[1]), u1 = fmaf(hF, F1, mom_cur[2]), u2 = fmaf(hF, F2, mom_cur[3]);
+                const float Pxx = fmaf(qF * F0, F0, mom_cur[4]), Pyy = fmaf(qF * F1, F1, mom_cur[5]);
+                const float Pzz = fmaf(qF * F2, F2, mom_cur[6]), Pxy = fmaf(qF * F0, F1, mom_cur[7]);
+                const float Pxz = fmaf(qF * F0, F2, mom_cur[8]), Pyz = fmaf(qF * F1, F2, mom_cur[9]);
+                // Hermite coefficients, pre-scaled: t(c) = K0 + sum K1 c + ... (see header)
+                const float Jx = fmaf(rho, u0, 0.5f * F0), Jy = fmaf(rho, u1, 0.5f * F1), Jz = fmaf(rho, u2, 0.5f * F2);
+                const float mxx = omega1 * Pxx, myy = omega1 * Pyy, mzz = omega1 * Pzz;
+                const float mxy = omega1 * Pxy, mxz = omega1 * Pxz, myz = omega1 * Pyz;
+                const float ru0 = rho * u0, ru1 = rho * u1, ru2 = rho * u2;
+                const float a2xx = fmaf(ru0, u0, mxx) + u0 * F0;
+                const float a2yy = fmaf(ru1, u1, myy) + u1 * F1;
+                const float a2zz = fmaf(ru2, u2, mzz) + u2 * F2;
+                const float a2xy = fmaf(ru0, u1, mxy) + 0.5f * (u0 * F1 + F0 * u1);
+                const float a2xz = fmaf(ru0, u2, mxz) + 0.5f * (u0 * F2 + F0 * u2);
+                const float a2yz = fmaf(ru1, u2, myz) + 0.5f * (u1 * F2 + F1 * u2);
+                // a3_aab = u_a (rho u_a u_b + 2 m_ab) + u_b m_aa
+                const float a3xxy = fmaf(u0, fmaf(ru0, u1, 2.0f * mxy), u1 * mxx);
+                const float a3xxz = fmaf(u0, fmaf(ru0, u2, 2.0f * mxz), u2 * mxx);
+                const float a3yyx = fmaf(u1, fmaf(ru1, u0, 2.0f * mxy), u0 * myy);
+                const float a3yyz = fmaf(u1, fmaf(ru1, u2, 2.0f * myz), u2 * myy);
+                const float a3zzx = fmaf(u2, fmaf(ru2, u0, 2.0f * mxz), u0 * mzz);
+                const float a3zzy = fmaf(u2, fmaf(ru2, u1, 2.0f * myz), u1 * mzz);
+                const float a3xyz = fmaf(ru0 * u1, u2, fmaf(u0, myz, fmaf(u1, mxz, u2 * mxy)));
+                const float K1x = 3.0f * Jx, K1y = 3.0f * Jy, K1z = 3.0f * Jz;
+                const float K2xx = 4.5f * a2xx, K2yy = 4.5f * a2yy, K2zz = 4.5f * a2zz;
+                const float K2xy = 9.0f * a2xy, K2xz = 9.0f * a2xz, K2yz = 9.0f * a2yz;
+                const float K3xxy = 13.5f * a3xxy, K3xxz = 13.5f * a3xxz, K3yyx = 13.5f * a3yyx;
+                const float K3yyz = 13.5f * a3yyz, K3zzx = 13.5f * a3zzx, K3zzy = 13.5f * a3zzy;
+                const float K3xyz = 27.0f * a3xyz;
+                // t = T0 + cz T1 + h(cz) T2; T0 = U0 + cy U1 + h(cy) U2 (per cx), etc.
+                float U0[3], U1[3], V0[3], W0[3];
+                quad3(0.0f, K1x, K2xx, U0[0], U0[1], U0[2]);  // tau = t - rho'
+                quad3(K1y, K2xy, K3xxy, U1[0], U1[1], U1[2]);
+                quad3(K1z, K2xz, K3xxz, V0[0], V0[1], V0[2]);
+                W0[0] = K2zz - K3zzx;
+                W0[1] = K2zz;
+                W0[2] = K2zz + K3zzx;
+#pragma unroll
+                for (int ix = 0; ix < 3; ++ix) {
+                    const float cx = (float)(ix - 1);
+                    const float U2 = fmaf(K3yyx, cx, K2yy);   // linear in cx
+                    const float V1 = fmaf(K3xyz, cx, K2yz);
+                    float T0[3], T1[3], T2[3];
+                    quad3(U0[ix], U1[ix], U2, T0[0], T0[1], T0[2]);
+                    quad3(V0[ix], V1, K3yyz, T1[0], T1[1], T1[2]);
+                    T2[0] = W0[ix] - K3zzy;
+                    T2[1] = W0[ix];
+                    T2[2] = W0[ix] + K3zzy;
+#pragma unroll
+                    for (int iy = 0; iy < 3; ++iy) {
+                        const int k = ix + 3 * iy;
+                        const float mid = fmaf(T2[iy], 2.0f / 3.0f, T0[iy]);
+                        t0[k] = fmaf(T2[iy], -1.0f / 3.0f, T0[iy]);
+                        tm[k] = mid - T1[iy];
+                        tp[k] = mid + T1[iy];
+                    }
+                }
+                // phase: base to every axis neighbour, +-a_e along +-e, phi - 6 base stays
+                const float phif = phi_to_float(phis);
+                const float omphi = (float)(kPhiOne - phis) * kPhiUlp;
+                const float gph = gamma * omphi;
+                const float h8 = 0.125f * phif * kPhiInvUlp;
+                base = (phis + 4) >> 3;
+                ax = __float2int_rn(h8 * fmaf(4.0f, u0, gph * n0));
+                ay = __float2int_rn(h8 * fmaf(4.0f, u1, gph * n1));
+                az = __float2int_rn(h8 * fmaf(4.0f, u2, gph * n2));
+
+                // ---- S5a: publish what crosses columns ----
+#pragma unroll
+                for (int cy = -1; cy <= 1; ++cy)
+#pragma unroll
+                    for (int cx = -1; cx <= 1; ++cx) {
+                        if (!cx && !cy) continue;
+                        const int k = (cx + 1) + 3 * (cy + 1);
+                        const int s = xy_slot(cx, cy);
+                        sm.xch[s][sidx] = tm[k];
+                        sm.xch[8 + s][sidx] = t0[k];
+                        sm.xch[16 + s][sidx] = tp[k];
+                    }
+                sm.xch[24][sidx] = __int_as_float(base + ax);  // +x
+                sm.xch[25][sidx] = __int_as_float(base - ax);  // -x
+                sm.xch[26][sidx] = __int_as_float(base + ay);  // +y
+                sm.xch[27][sidx] = __int_as_float(base - ay);  // -y
+                sm.xch[28][sidx] = rp;
+            }
+            __syncthreads();
+
+            // ---- S5b/S6: gather at the destination and finish plane r - 1 ----
+            if (is_dst) {
+                float gm[9], g0[9], gp[9];
+                const float rp_own = mom_cur[0];
+                gm[4] = tm[4];
+                g0[4] = t0[4];
+                gp[4] = tp[4];
+#pragma unroll
+                for (int cy = -1; cy <= 1; ++cy)
+#pragma unroll
+                    for (int cx = -1; cx <= 1; ++cx) {
+                        if (!cx && !cy) continue;
+                        const int k = (cx + 1) + 3 * (cy + 1);
+                        const int s = xy_slot(cx, cy);
+                        const int src = (sy - cy) * SX + (sx - cx);
+                        const float drp = sm.xch[28][src] - rp_own;
+                        gm[k] = sm.xch[s][src] + drp;
+                        g0[k] = sm.xch[8 + s][src] + drp;
+                        gp[k] = sm.xch[16 + s][src] + drp;
+                    }
+                float Xm[6], X0[6], Xp[6];
+                xy_moments(gm, Xm);
+                xy_moments(g0, X0);
+                xy_moments(gp, Xp);
+                Xm[0] += rp_own;
+                X0[0] += rp_own;
+                Xp[0] += rp_own;
+                const int32_t pin = __float_as_int(sm.xch[24][sidx - 1]) + __float_as_int(sm.xch[25][sidx + 1]) +
+                                    __float_as_int(sm.xch[26][sidx - SX]) + __float_as_int(sm.xch[27][sidx + SX]);
+                // destination plane r - 1: X(-1) from source plane r, X(0) = XB, X(+1) = XA
+                const int zd = r - 1;
+                if (dst_xy && zd >= z0 && zd < z1 && (g.per[2] || (zd > 0 && zd < g.nz - 1))) {
+                    const Tr3 m00 = tr3(Xm[0], XB[0], XA[0]);  // rho', j_z, H_zz
+                    const Tr3 m10 = tr3(Xm[1], XB[1], XA[1]);  // j_x, H_xz
+                    const Tr3 m01 = tr3(Xm[2], XB[2], XA[2]);  // j_y, H_yz
+                    const float Hxx = tr3_m0(Xm[3], XB[3], XA[3]);
+                    const float Hyy = tr3_m0(Xm[4], XB[4], XA[4]);
+                    const float Hxy = tr3_m0(Xm[5], XB[5], XA[5]);
+                    const float drho = m00.m0;
+                    const float jx = m10.m0, jy = m01.m0, jz = m00.m1;
+                    const float inv = 1.0f / (1.0f + drho);
+                    const long long id = (long long)gxs + (long long)g.nx * gys + plane * zd;
+                    T *o = (T *)out.mom;
+                    S::store(o, id, drho, sc.inv_s2);
+                    S::store(o + g.ld, id, jx * inv, sc.inv_s1);
+                    S::store(o + 2 * g.ld, id, jy * inv, sc.inv_s1);
+                    S::store(o + 3 * g.ld, id, jz * inv, sc.inv_s1);
+                    S::store(o + 4 * g.ld, id, fmaf(-jx * inv, jx, Hxx), sc.inv_s2);
+                    S::store(o + 5 * g.ld, id, fmaf(-jy * inv, jy, Hyy), sc.inv_s2);
+                    S::store(o + 6 * g.ld, id, fmaf(-jz * inv, jz, m00.m2), sc.inv_s2);
+                    S::store(o + 7 * g.ld, id, fmaf(-jx * inv, jy, Hxy), sc.inv_s2);
+                    S::store(o + 8 * g.ld, id, fmaf(-jx * inv, jz, m10.m1), sc.inv_s2);
+                    S::store(o + 9 * g.ld, id, fmaf(-jy * inv, jz, m01.m1), sc.inv_s2);
+                    out.phi[id] = PA + (base - az);
+                }
+                // carry: plane r gets X(+1) = XC, X(0) = X0; plane r+1 gets X(+1) = Xp
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    XA[k] = XC[k];
+                    XB[k] = X0[k];
+                    XC[k] = Xp[k];
+                }
+                PA = PC + (phis - 6 * base) + pin;
+                PC = base + az;
+            }
+        }
+    }
+}
+
+}  // namespace fused
+
+// Launch the fused step over the whole lattice.
+hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int lz, hipStream_t s) {
+    using namespace fused;
+    const int tiles_x = (c->geo.nx + TX - 1) / TX, tiles_y = (c->geo.ny + TY - 1) / TY;
+    const int chunks = (c->geo.nz + lz - 1) / lz;
+    const unsigned blocks = (unsigned)tiles_x * tiles_y * chunks;
+    switch (c->storage) {
+    case ST_FP32:
+        hipLaunchKernelGGL(k_step_fused<ST_FP32>, dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in, out,
+                           lz, tiles_x, tiles_y);
+        break;
+    case ST_FP16:
+        hipLaunchKernelGGL(k_step_fused<ST_FP16>, dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in, out,
+                           lz, tiles_x, tiles_y);
+        break;
+    default:
+        hipLaunchKernelGGL(k_step_fused<ST_BF16>, dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in, out,
+                           lz, tiles_x, tiles_y);
+        break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace tslb

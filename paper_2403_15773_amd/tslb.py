@@ -26,9 +26,10 @@ STORAGE = {"fp32": STORE_FP32, "fp16": STORE_FP16, "bf16": STORE_BF16}
 EXPORTS = [
     "tslb_params_init", "tslb_params_size", "tslb_required_bytes", "tslb_create", "tslb_set_state", "tslb_step", "tslb_sync",
     "tslb_moments", "tslb_phase", "tslb_state_bytes", "tslb_get_state_raw", "tslb_set_state_raw",
-    "tslb_diagnostics", "tslb_step_index", "tslb_set_timing", "tslb_last_step_kernel_ms", "tslb_destroy",
-    "tslb_last_error",
+    "tslb_diagnostics", "tslb_step_index", "tslb_set_timing", "tslb_last_step_kernel_ms", "tslb_set_kernel",
+    "tslb_destroy", "tslb_last_error",
 ]
+KERNEL_FUSED, KERNEL_GATHER = 0, 1
 
 
 class TslbError(RuntimeError):
@@ -89,6 +90,7 @@ def load_library(path: str = LIB_PATH):
             "tslb_step_index": (ctypes.c_int64, [vp]),
             "tslb_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
             "tslb_last_step_kernel_ms": (ctypes.c_double, [vp]),
+            "tslb_set_kernel": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
             "tslb_destroy": (None, [vp]),
             "tslb_last_error": (ctypes.c_char_p, [vp]),
         }
@@ -225,3 +227,7 @@ class Simulation:
 
     def last_step_kernel_ms(self):
         return self.lib.tslb_last_step_kernel_ms(self.h)
+
+    def set_kernel(self, kernel="fused", chunk_z=0):
+        k = {"fused": KERNEL_FUSED, "gather": KERNEL_GATHER}[kernel] if isinstance(kernel, str) else int(kernel)
+        self._check(self.lib.tslb_set_kernel(self.h, k, int(chunk_z)))

@@ -191,3 +191,65 @@ def test_non_finite_state_is_reported():
     assert ei.value.code == E_UNSTABLE
     assert s.step_index == 2
     assert not s.diagnostics()["finite"]
+
+
+def test_partial_tiles_parity():
+    """Sizes that leave partial 32 x 16 tiles and a short z chunk (40 x 20 x 11)."""
+    _say("partial tiles 40x20x11 fp32 40 steps")
+    nx, ny, nz = 40, 20, 11
+    x, y, z = inputs.grid_coords(nx, ny, nz)
+    st = inputs.quiescent(nx, ny, nz)
+    st["phi"] = 0.5 * (1 - np.tanh(2 * (np.sqrt((x - 20.5) ** 2 + (y - 9.2) ** 2 + (z - 5.1) ** 2) - 4.0) / 3.0))
+    node = np.arange(nx * ny * nz, dtype=np.uint64)
+    st["u"] = 0.01 * np.stack([inputs.noise(8, 0, 0, node, a).reshape(nz, ny, nx) for a in range(3)])
+    p = dict(nx=nx, ny=ny, nz=nz, nu=0.03, sigma=0.02, width=3.0, bc=(0,) * 6)
+    g, r = run_both(p, st, 40)
+    assert_parity(g, r, TOL_FP32, "partial-tiles")
+
+
+def test_partial_tiles_jet_parity():
+    """A jet whose lateral sizes are not tile multiples (40 x 36 x 50), 150 steps."""
+    _say("partial-tile jet 40x36x50 fp32 150 steps")
+    p = inputs.jet_params(40, 36, 50, d=10.0, u=0.05, re=500.0, we=50.0, seed=12)
+    g, r = run_both(p, inputs.quiescent(40, 36, 50), 150)
+    assert_parity(g, r, TOL_FP32, "partial-tile jet")
+
+
+def test_fused_result_does_not_depend_on_z_chunking():
+    from paper_2403_15773_amd.tslb import Simulation
+    _say("chunk invariance droplet 32^3")
+    st = _f32(inputs.droplet(32, 8.0, 3.0, noise_amp=1e-3, seed=1))
+    outs = []
+    for chunk in (1, 5, 32):
+        s = Simulation(**inputs.droplet_params(32), eps=EPS)
+        s.set_kernel("fused", chunk)
+        s.set_state(**st)
+        s.step(30)
+        outs.append(s.get_state_raw())
+        s.close()
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_fused_matches_gather_on_full_jet():
+    """128 x 128 x 512 jet (D = 20, Re = 5000, We = 100), 400 steps from rest: the
+    fused kernel against the simple gather kernel, every node.  Two independent
+    binary32 results, each within 1e-5 of exact arithmetic, so the bound is 2e-5."""
+    from paper_2403_15773_amd.tslb import Simulation
+    _say("fused vs gather, jet 128x128x512, 400 steps")
+    p = inputs.WORKLOADS["jet128"]["params"]
+    st = _f32(inputs.quiescent(p["nx"], p["ny"], p["nz"]))
+    res = {}
+    for k in ("fused", "gather"):
+        s = Simulation(**p, eps=EPS)
+        s.set_kernel(k)
+        s.set_state(**st)
+        s.step(400)
+        res[k] = s.physical()
+        s.close()
+    ref = {kk: v.astype(np.float64) for kk, v in res["gather"].items() if kk != "rho_dev"}
+    ref["rho"] = 1.0 + res["gather"]["rho_dev"].astype(np.float64)
+    errs = field_errors(res["fused"], ref)
+    _say("fused-vs-gather " + " ".join("%s=%.2e" % (kk, v[0]) for kk, v in errs.items()))
+    assert res["gather"]["u"][2].max() > 0.04  # the jet is there
+    bad = {kk: v for kk, v in errs.items() if not v[0] <= 2 * TOL_FP32}
+    assert not bad, bad
