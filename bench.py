@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--workload", default="jet128", choices=["jet128", "jet512", "droplet32"])
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-oracle sample budget (0 = skip)")
+    ap.add_argument("--copy-mib", type=int, default=1024, help="size of the copy-kernel ceiling probe (0 = skip)")
+    ap.add_argument("--kernel", default="fused", choices=["fused", "gather"])
     return ap.parse_args()
 
 
@@ -95,7 +97,15 @@ def main():
 
     p, st = workload_state(a.workload)
     nodes = p["nx"] * p["ny"] * p["nz"]
+    from paper_2403_15773_amd.tslb import copy_bandwidth
+    copy = None
+    if a.copy_mib > 0:
+        gbps, cms = copy_bandwidth(a.copy_mib << 20, iters=20)
+        copy = {"gbps": gbps, "ms": cms, "bytes_moved": 2 * (a.copy_mib << 20)}
+        print("bench: copy-kernel ceiling %.0f GB/s (%d MiB read + written, %.3f ms)" % (gbps, 2 * a.copy_mib, cms),
+              file=sys.stderr, flush=True)
     sim = Simulation(**p, eps=1e-4, storage=a.storage, device=0)
+    sim.set_kernel(a.kernel)
     sim.set_state(rho_dev=np.asarray(st["rho"] - 1.0, np.float32), u=np.asarray(st["u"], np.float32),
                   P=np.asarray(st["P"], np.float32), phi=np.asarray(st["phi"], np.float32))
     print("bench: %s %s, warmup %d" % (a.workload, a.storage, a.warmup), file=sys.stderr, flush=True)
@@ -132,7 +142,9 @@ def main():
         "config": describe(a.workload, p) | {"storage": a.storage, "finite": diag["finite"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
-                     "kernel": "fused step", "bytes_per_node": bpn, "kernel_ms": kernel_ms},
+                     "kernel": "%s step" % a.kernel, "bytes_per_node": bpn, "kernel_ms": kernel_ms,
+                     "copy_ceiling": copy["gbps"] if copy else None,
+                     "frac_of_copy_ceiling": achieved / copy["gbps"] if (copy and achieved) else None},
         "cpu_baseline": cpu_baseline(a.workload, p, st, a.cpu_seconds),
     }
     print(json.dumps(rec), flush=True)

@@ -164,6 +164,13 @@ double tslb_last_step_kernel_ms(tslb_ctx *ctx);
  * value).  Both kernels compute the same step up to rounding. */
 int tslb_set_kernel(tslb_ctx *ctx, int kernel, int chunk_z);
 
+/* Measurement utility: copy `bytes` (a multiple of 16) between two device
+ * buffers it allocates on `device`, `iters` times with a plain streaming copy
+ * kernel, and report the median rate as read + written bytes per second in GB/s
+ * (*gbps) and the median kernel time in ms (*ms).  Used as the measured HBM
+ * ceiling and as the reference for scaling hardware byte counters. */
+int tslb_copy_bandwidth(int device, size_t bytes, int iters, double *gbps, double *ms);
+
 /* Release the context and everything it allocated. */
 void tslb_destroy(tslb_ctx *ctx);
 

@@ -1,5 +1,6 @@
 // C-ABI of the TSLB library: context lifetime, state transfer, the step loop
 // and diagnostics.  Declarations and contracts are in include/tslb.h.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -250,11 +251,15 @@ int tslb_step(tslb_ctx *c, int64_t nsteps) {
         }
         tm.used = 0;
     }
+    // The fused kernel writes the boundary layers of the state it produces; the
+    // current state's layers are filled once here (the fill is idempotent).
+    const bool fused = c->kernel == TSLB_KERNEL_FUSED;
+    if (fused && nsteps > 0) HIP_TRY(c, launch_boundary(c, c->buf[c->cur], c->step, c->stream));
     for (int64_t s = 0; s < nsteps; ++s) {
-        HIP_TRY(c, launch_boundary(c, c->buf[c->cur], c->step, c->stream));
+        if (!fused) HIP_TRY(c, launch_boundary(c, c->buf[c->cur], c->step, c->stream));
         bool timing = tm.enabled && timed < max_timed;
         if (timing) HIP_TRY(c, hipEventRecord(tm.ev[2 * timed], c->stream));
-        HIP_TRY(c, launch_step(c, c->buf[c->cur], c->buf[c->cur ^ 1], c->stream));
+        HIP_TRY(c, launch_step(c, c->buf[c->cur], c->buf[c->cur ^ 1], c->step + 1, c->stream));
         if (timing) {
             HIP_TRY(c, hipEventRecord(tm.ev[2 * timed + 1], c->stream));
             ++timed;
@@ -387,6 +392,47 @@ double tslb_last_step_kernel_ms(tslb_ctx *c) {
         total += ms;
     }
     return total / (double)c->timer.used;
+}
+
+int tslb_copy_bandwidth(int device, size_t bytes, int iters, double *gbps, double *ms) {
+    if (bytes == 0 || bytes % 16 != 0 || iters < 1 || !gbps || !ms)
+        return fail(nullptr, TSLB_E_INVAL, "bytes must be a positive multiple of 16 and iters >= 1");
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(nullptr, TSLB_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    void *a = nullptr, *b = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<float> times;
+    int rc = TSLB_OK;
+    e = hipMalloc(&a, bytes);
+    if (e == hipSuccess) e = hipMalloc(&b, bytes);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipMemsetAsync(a, 0, bytes, s);
+    for (int k = 0; e == hipSuccess && k < iters + 1; ++k) {
+        e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = launch_copy_probe(a, b, bytes, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e == hipSuccess && k > 0) times.push_back(t);  // the first launch is a warm-up
+    }
+    if (e != hipSuccess) {
+        rc = fail(nullptr, TSLB_E_DEVICE, std::string("copy probe: ") + hipGetErrorString(e));
+    } else {
+        std::sort(times.begin(), times.end());
+        const double med = times[times.size() / 2];
+        *ms = med;
+        *gbps = 2.0 * (double)bytes / (med * 1e-3) / 1e9;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    return rc;
 }
 
 void tslb_destroy(tslb_ctx *c) {

@@ -137,4 +137,50 @@ __device__ __forceinline__ float noise_xi(unsigned long long key, unsigned long 
     return (float)(unsigned int)(h >> 40) * (1.0f / 8388608.0f) - 1.0f;
 }
 
+// ---- boundary-layer rules (Eqs. 9, 10) ------------------------------------
+
+// Face a boundary node belongs to (0..5 = -x,+x,-y,+y,-z,+z): the face of the
+// highest non-periodic axis on which it lies (z, then y, then x); -1 if interior.
+__device__ __forceinline__ int boundary_face(const Geo &g, int x, int y, int z) {
+    if (!g.per[2] && (z == 0 || z == g.nz - 1)) return z == 0 ? 4 : 5;
+    if (!g.per[1] && (y == 0 || y == g.ny - 1)) return y == 0 ? 2 : 3;
+    if (!g.per[0] && (x == 0 || x == g.nx - 1)) return x == 0 ? 0 : 1;
+    return -1;
+}
+
+// Raw moments m[10] (rho', ubar, Q) and phase of boundary node (x, y) on `face`
+// at step `step`, given those of its nearest interior node on input: the rule
+// imposes density and/or velocity and keeps the copied non-equilibrium part.
+__device__ __forceinline__ void apply_boundary_rule(const Phys &ph, const Geo &g, int face, int x, int y,
+                                                    unsigned long long step, float m[10], int32_t &phi) {
+    const int axis = face >> 1;
+    switch (ph.bc[face]) {
+    case 1:  // free slip: no normal velocity, no normal-tangential stress
+        m[1 + axis] = 0.f;
+        if (axis == 0) { m[7] = 0.f; m[8] = 0.f; }
+        if (axis == 1) { m[7] = 0.f; m[9] = 0.f; }
+        if (axis == 2) { m[8] = 0.f; m[9] = 0.f; }
+        break;
+    case 4:  // no slip
+        m[1] = m[2] = m[3] = 0.f;
+        break;
+    case 3:  // outflow: unit density
+        m[0] = 0.f;
+        break;
+    case 2: {  // inlet disc on -z: u = U s(r)(1 + a xi) e_z, phi = s(r)
+        const float dx = x - 0.5f * (g.nx - 1), dy = y - 0.5f * (g.ny - 1);
+        const float r = sqrtf(dx * dx + dy * dy);
+        const float s = 0.5f * (1.0f - tanhf(2.0f * (r - 0.5f * ph.inlet_d) / ph.width));
+        const float xi = noise_xi(ph.noise_key, 1ull, step, (unsigned long long)(x + (long long)g.nx * y), 2ull);
+        m[1] = 0.f;
+        m[2] = 0.f;
+        m[3] = ph.inlet_u * s * (1.0f + ph.inlet_noise * xi);
+        phi = phi_from_float(s);
+        break;
+    }
+    default:
+        break;
+    }
+}
+
 }  // namespace tslb

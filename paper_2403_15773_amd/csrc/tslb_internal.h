@@ -71,8 +71,10 @@ hipError_t launch_geometry(const tslb_ctx *c, const int32_t *phi, float *geo_pla
 hipError_t launch_set_state(const tslb_ctx *c, const float *stage, float *geo_planes, StateView out, hipStream_t s);
 hipError_t launch_readout(const tslb_ctx *c, StateView in, const float *geo_planes, float *stage, hipStream_t s);
 hipError_t launch_boundary(const tslb_ctx *c, StateView st, int64_t step, hipStream_t s);
-hipError_t launch_step(const tslb_ctx *c, StateView in, StateView out, hipStream_t s);
-hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int lz, hipStream_t s);
+hipError_t launch_step(const tslb_ctx *c, StateView in, StateView out, int64_t step_next, hipStream_t s);
+hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int lz, int64_t step_next,
+                             hipStream_t s);
+hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
 hipError_t launch_diagnostics(const tslb_ctx *c, StateView st, const Scratch &sc, hipStream_t s);
 size_t diagnostics_blocks(const tslb_ctx *c);
 

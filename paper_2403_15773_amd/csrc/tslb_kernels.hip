@@ -210,34 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_boundary(Geo g, Phys ph, Scales sc, 
     float m[10];
     load_raw<ST>(st, g, sc, idF, m);
     int32_t phi = st.phi[idF];
-    switch (ph.bc[face]) {
-    case TSLB_BC_FREESLIP:
-        m[1 + axis] = 0.f;
-        // Q components with exactly one index on the wall normal: xy, xz, yz = 7, 8, 9
-        if (axis == 0) { m[7] = 0.f; m[8] = 0.f; }
-        if (axis == 1) { m[7] = 0.f; m[9] = 0.f; }
-        if (axis == 2) { m[8] = 0.f; m[9] = 0.f; }
-        break;
-    case TSLB_BC_NOSLIP:
-        m[1] = m[2] = m[3] = 0.f;
-        break;
-    case TSLB_BC_OUTFLOW:
-        m[0] = 0.f;
-        break;
-    case TSLB_BC_INLET: {
-        float dx = v[0] - 0.5f * (g.nx - 1), dy = v[1] - 0.5f * (g.ny - 1);
-        float r = sqrtf(dx * dx + dy * dy);
-        float s = 0.5f * (1.0f - tanhf(2.0f * (r - 0.5f * ph.inlet_d) / ph.width));
-        float xi = noise_xi(ph.noise_key, 1ull, step, (unsigned long long)(v[0] + (long long)g.nx * v[1]), 2ull);
-        m[1] = 0.f;
-        m[2] = 0.f;
-        m[3] = ph.inlet_u * s * (1.0f + ph.inlet_noise * xi);
-        phi = phi_from_float(s);
-        break;
-    }
-    default:
-        break;
-    }
+    apply_boundary_rule(ph, g, face, v[0], v[1], step, m, phi);
     store_raw<ST>(st, g, sc, id, m);
     st.phi[id] = phi;
 }
@@ -492,10 +465,28 @@ hipError_t launch_diagnostics(const tslb_ctx *c, StateView st, const Scratch &sc
 
 namespace tslb {
 
-// One step from `in` to `out`: the fused kernel, or (TSLB_KERNEL_GATHER) the
-// materialised interface geometry of `in` followed by the gather update.
-hipError_t launch_step(const tslb_ctx *c, StateView in, StateView out, hipStream_t s) {
-    if (c->kernel == TSLB_KERNEL_FUSED) return launch_step_fused(c, in, out, c->chunk_z, s);
+// Plain streaming copy (16-byte vectors, grid-stride): the measured HBM ceiling
+// and the reference for scaling hardware byte counters.
+__global__ __launch_bounds__(kBlock) void k_copy_probe(const float4 *__restrict__ src, float4 *__restrict__ dst,
+                                                       long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s) {
+    const long long n = (long long)(bytes / 16);
+    const long long blocks = (n + kBlock - 1) / kBlock;  // one 16-byte vector per thread
+    hipLaunchKernelGGL(k_copy_probe, dim3((unsigned)(blocks < 0x7fffffff ? blocks : 0x7fffffff)), dim3(kBlock), 0, s,
+                       (const float4 *)src, (float4 *)dst, n);
+    return hipGetLastError();
+}
+
+// One step from `in` (step t) to `out` (step t+1): the fused kernel, which also
+// writes the boundary layers of step t+1, or (TSLB_KERNEL_GATHER) the
+// materialised interface geometry of `in` followed by the gather update of the
+// interior (the caller fills the boundary layers separately).
+hipError_t launch_step(const tslb_ctx *c, StateView in, StateView out, int64_t step_next, hipStream_t s) {
+    if (c->kernel == TSLB_KERNEL_FUSED) return launch_step_fused(c, in, out, c->chunk_z, step_next, s);
     hipError_t e = launch_geometry(c, in.phi, c->scratch.geo, s);
     if (e != hipSuccess) return e;
     return launch_step_gather(c, in, c->scratch.geo, out, s);

@@ -44,7 +44,7 @@ constexpr int GX = TX + 4, GY = TY + 4, NGEO = GX * GY;   // geometry: 36 x 20
 constexpr int PX = TX + 6, PY = TY + 6, NPHI = PX * PY;   // phase field: 38 x 22
 constexpr int NDST = TX * TY;                              // 512
 constexpr int NT = 640;                                    // threads per workgroup
-constexpr int NXCH = 29;                                   // exchange slots per source
+constexpr int NXCH = 35;                                   // exchange slots per source
 
 static_assert(NSRC <= NT && NDST <= NSRC, "tile does not fit the workgroup");
 static_assert(NPHI <= 2 * NT && NGEO <= 2 * NT, "staging loops assume two items per thread");
@@ -114,16 +114,28 @@ __device__ __forceinline__ void xy_moments(const float t[9], float X[6]) {
 
 template <int ST>
 __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, StateView in, StateView out, int lz,
-                                                   int tiles_x, int tiles_y) {
+                                                   int tiles_x, int tiles_y, unsigned long long step_next,
+                                                   int has_bnd) {
     __shared__ Smem sm;
     using S = Store<ST>;
     using T = typename S::T;
 
     // ---- tile and chunk of this workgroup ----
-    const int b = blockIdx.x;
-    const int tile = b % (tiles_x * tiles_y);
-    const int chunk = b / (tiles_x * tiles_y);
-    const int x0 = (tile % tiles_x) * TX, y0 = (tile / tiles_x) * TY;
+    // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+    // L2.  Work item w is assigned so that every XCD receives a contiguous range
+    // of w: the tiles of one z chunk then run side by side on one XCD and their
+    // overlapping halos are served by that XCD's L2 instead of HBM.
+    const int nb = gridDim.x, q8 = nb >> 3, rem8 = nb & 7;
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int w = (xcd < rem8 ? xcd * (q8 + 1) : rem8 * (q8 + 1) + (xcd - rem8) * q8) + slot;
+    const int tile = w % (tiles_x * tiles_y);
+    const int chunk = w / (tiles_x * tiles_y);
+    // The tile owns columns [xo, xo + TX) x [yo, yo + TY); its origin (x0, y0) is
+    // pulled inward at the high edge so that all TX x TY columns lie in the
+    // lattice (a wall column's nearest interior node is then always in the tile).
+    const int xo = (tile % tiles_x) * TX, yo = (tile / tiles_x) * TY;
+    const int x0 = g.nx > TX ? min(xo, g.nx - TX) : 0;
+    const int y0 = g.ny > TY ? min(yo, g.ny - TY) : 0;
     const int z0 = chunk * lz;
     const int z1 = min(z0 + lz, g.nz);  // destination planes [z0, z1)
     const int t = threadIdx.x;
@@ -150,8 +162,15 @@ __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, St
     const long long col_src = (long long)cxs + (long long)g.nx * cys;
     const bool src_bnd_xy = (!g.per[0] && (gxs <= 0 || gxs >= g.nx - 1)) ||
                             (!g.per[1] && (gys <= 0 || gys >= g.ny - 1));
-    // destination validity in x, y (interior of the lattice, inside the domain)
-    const bool dst_xy = is_dst && gxs < g.nx && gys < g.ny && !src_bnd_xy;
+    // Destination columns: every owned column, walls included.  A wall column
+    // finishes the moments of its nearest interior node x_F (one node in from the
+    // wall) and stores them through its face rule (Eqs. 9, 10), so each
+    // destination thread reads the exchange buffer around fidx = x_F.
+    const bool owned = is_dst && gxs >= xo && gxs < xo + TX && gxs < g.nx && gys >= yo && gys < yo + TY &&
+                       gys < g.ny;
+    const int dxf = (!g.per[0] && gxs == 0) ? 1 : ((!g.per[0] && gxs == g.nx - 1) ? -1 : 0);
+    const int dyf = (!g.per[1] && gys == 0) ? 1 : ((!g.per[1] && gys == g.ny - 1) ? -1 : 0);
+    const int fidx = (sy + dyf) * SX + (sx + dxf);
 
     // ---- staging columns of the phase field (<= 2 per thread) ----
     long long col_phi[2];
@@ -180,7 +199,7 @@ __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, St
     float XA[6], XB[6], XC[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) XA[k] = XB[k] = XC[k] = 0.f;
-    int32_t PA = 0, PC = 0;
+    int32_t PA = 0, PC = 0;  // phase partial sums of planes r - 1 and r (column x_F)
 
     // prefetched raw moments of the next source plane (own column)
     float mom[10];
@@ -407,16 +426,22 @@ __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, St
                 sm.xch[26][sidx] = __int_as_float(base + ay);  // +y
                 sm.xch[27][sidx] = __int_as_float(base - ay);  // -y
                 sm.xch[28][sidx] = rp;
+                sm.xch[29][sidx] = __int_as_float(phis - 6 * base);  // rest
+                sm.xch[30][sidx] = __int_as_float(base + az);        // +z
+                sm.xch[31][sidx] = __int_as_float(base - az);        // -z
+                sm.xch[32][sidx] = tm[4];
+                sm.xch[33][sidx] = t0[4];
+                sm.xch[34][sidx] = tp[4];
             }
             __syncthreads();
 
             // ---- S5b/S6: gather at the destination and finish plane r - 1 ----
             if (is_dst) {
                 float gm[9], g0[9], gp[9];
-                const float rp_own = mom_cur[0];
-                gm[4] = tm[4];
-                g0[4] = t0[4];
-                gp[4] = tp[4];
+                const float rp_ref = sm.xch[28][fidx];
+                gm[4] = sm.xch[32][fidx];
+                g0[4] = sm.xch[33][fidx];
+                gp[4] = sm.xch[34][fidx];
 #pragma unroll
                 for (int cy = -1; cy <= 1; ++cy)
 #pragma unroll
@@ -424,8 +449,8 @@ __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, St
                         if (!cx && !cy) continue;
                         const int k = (cx + 1) + 3 * (cy + 1);
                         const int s = xy_slot(cx, cy);
-                        const int src = (sy - cy) * SX + (sx - cx);
-                        const float drp = sm.xch[28][src] - rp_own;
+                        const int src = fidx - cy * SX - cx;
+                        const float drp = sm.xch[28][src] - rp_ref;
                         gm[k] = sm.xch[s][src] + drp;
                         g0[k] = sm.xch[8 + s][src] + drp;
                         gp[k] = sm.xch[16 + s][src] + drp;
@@ -434,14 +459,17 @@ __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, St
                 xy_moments(gm, Xm);
                 xy_moments(g0, X0);
                 xy_moments(gp, Xp);
-                Xm[0] += rp_own;
-                X0[0] += rp_own;
-                Xp[0] += rp_own;
-                const int32_t pin = __float_as_int(sm.xch[24][sidx - 1]) + __float_as_int(sm.xch[25][sidx + 1]) +
-                                    __float_as_int(sm.xch[26][sidx - SX]) + __float_as_int(sm.xch[27][sidx + SX]);
+                Xm[0] += rp_ref;
+                X0[0] += rp_ref;
+                Xp[0] += rp_ref;
+                const int32_t pin = __float_as_int(sm.xch[24][fidx - 1]) + __float_as_int(sm.xch[25][fidx + 1]) +
+                                    __float_as_int(sm.xch[26][fidx - SX]) + __float_as_int(sm.xch[27][fidx + SX]);
+                const int32_t prest = __float_as_int(sm.xch[29][fidx]);
+                const int32_t pup = __float_as_int(sm.xch[30][fidx]);
+                const int32_t pdown = __float_as_int(sm.xch[31][fidx]);
                 // destination plane r - 1: X(-1) from source plane r, X(0) = XB, X(+1) = XA
                 const int zd = r - 1;
-                if (dst_xy && zd >= z0 && zd < z1 && (g.per[2] || (zd > 0 && zd < g.nz - 1))) {
+                if (owned && zd >= z0 && zd < z1 && (g.per[2] || (zd > 0 && zd < g.nz - 1))) {
                     const Tr3 m00 = tr3(Xm[0], XB[0], XA[0]);  // rho', j_z, H_zz
                     const Tr3 m10 = tr3(Xm[1], XB[1], XA[1]);  // j_x, H_xz
                     const Tr3 m01 = tr3(Xm[2], XB[2], XA[2]);  // j_y, H_yz
@@ -451,19 +479,53 @@ __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, St
                     const float drho = m00.m0;
                     const float jx = m10.m0, jy = m01.m0, jz = m00.m1;
                     const float inv = 1.0f / (1.0f + drho);
-                    const long long id = (long long)gxs + (long long)g.nx * gys + plane * zd;
+                    float m[10];
+                    m[0] = drho;
+                    m[1] = jx * inv;
+                    m[2] = jy * inv;
+                    m[3] = jz * inv;
+                    m[4] = fmaf(-jx * inv, jx, Hxx);
+                    m[5] = fmaf(-jy * inv, jy, Hyy);
+                    m[6] = fmaf(-jz * inv, jz, m00.m2);
+                    m[7] = fmaf(-jx * inv, jy, Hxy);
+                    m[8] = fmaf(-jx * inv, jz, m10.m1);
+                    m[9] = fmaf(-jy * inv, jz, m01.m1);
+                    const int32_t phin = PA + pdown;
                     T *o = (T *)out.mom;
-                    S::store(o, id, drho, sc.inv_s2);
-                    S::store(o + g.ld, id, jx * inv, sc.inv_s1);
-                    S::store(o + 2 * g.ld, id, jy * inv, sc.inv_s1);
-                    S::store(o + 3 * g.ld, id, jz * inv, sc.inv_s1);
-                    S::store(o + 4 * g.ld, id, fmaf(-jx * inv, jx, Hxx), sc.inv_s2);
-                    S::store(o + 5 * g.ld, id, fmaf(-jy * inv, jy, Hyy), sc.inv_s2);
-                    S::store(o + 6 * g.ld, id, fmaf(-jz * inv, jz, m00.m2), sc.inv_s2);
-                    S::store(o + 7 * g.ld, id, fmaf(-jx * inv, jy, Hxy), sc.inv_s2);
-                    S::store(o + 8 * g.ld, id, fmaf(-jx * inv, jz, m10.m1), sc.inv_s2);
-                    S::store(o + 9 * g.ld, id, fmaf(-jy * inv, jz, m01.m1), sc.inv_s2);
-                    out.phi[id] = PA + (base - az);
+                    // the node itself: interior, or on an x/y wall (face rule of step t+1)
+                    {
+                        float mo[10];
+#pragma unroll
+                        for (int k = 0; k < 10; ++k) mo[k] = m[k];
+                        int32_t po = phin;
+                        if (dxf | dyf) {
+                            const int face = boundary_face(g, gxs, gys, zd);
+                            apply_boundary_rule(ph, g, face, gxs, gys, step_next, mo, po);
+                        }
+                        const long long id = (long long)gxs + (long long)g.nx * gys + plane * zd;
+                        S::store(o, id, mo[0], sc.inv_s2);
+#pragma unroll
+                        for (int k = 1; k < 4; ++k) S::store(o + k * g.ld, id, mo[k], sc.inv_s1);
+#pragma unroll
+                        for (int k = 4; k < 10; ++k) S::store(o + k * g.ld, id, mo[k], sc.inv_s2);
+                        out.phi[id] = po;
+                    }
+                    // the z walls of this column take the values of planes 1 and nz-2
+                    if (!g.per[2] && (zd == 1 || zd == g.nz - 2)) {
+                        const int zb = zd == 1 ? 0 : g.nz - 1;
+                        float mb[10];
+#pragma unroll
+                        for (int k = 0; k < 10; ++k) mb[k] = m[k];
+                        int32_t pb = phin;
+                        apply_boundary_rule(ph, g, zd == 1 ? 4 : 5, gxs, gys, step_next, mb, pb);
+                        const long long ib = (long long)gxs + (long long)g.nx * gys + plane * zb;
+                        S::store(o, ib, mb[0], sc.inv_s2);
+#pragma unroll
+                        for (int k = 1; k < 4; ++k) S::store(o + k * g.ld, ib, mb[k], sc.inv_s1);
+#pragma unroll
+                        for (int k = 4; k < 10; ++k) S::store(o + k * g.ld, ib, mb[k], sc.inv_s2);
+                        out.phi[ib] = pb;
+                    }
                 }
                 // carry: plane r gets X(+1) = XC, X(0) = X0; plane r+1 gets X(+1) = Xp
 #pragma unroll
@@ -472,8 +534,8 @@ __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, St
                     XB[k] = X0[k];
                     XC[k] = Xp[k];
                 }
-                PA = PC + (phis - 6 * base) + pin;
-                PC = base + az;
+                PA = PC + prest + pin;
+                PC = pup;
             }
         }
     }
@@ -482,7 +544,8 @@ __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, St
 }  // namespace fused
 
 // Launch the fused step over the whole lattice.
-hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int lz, hipStream_t s) {
+hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int lz, int64_t step_next,
+                             hipStream_t s) {
     using namespace fused;
     const int tiles_x = (c->geo.nx + TX - 1) / TX, tiles_y = (c->geo.ny + TY - 1) / TY;
     const int chunks = (c->geo.nz + lz - 1) / lz;
@@ -490,15 +553,15 @@ hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int
     switch (c->storage) {
     case ST_FP32:
         hipLaunchKernelGGL(k_step_fused<ST_FP32>, dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in, out,
-                           lz, tiles_x, tiles_y);
+                           lz, tiles_x, tiles_y, (unsigned long long)step_next, c->has_boundary ? 1 : 0);
         break;
     case ST_FP16:
         hipLaunchKernelGGL(k_step_fused<ST_FP16>, dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in, out,
-                           lz, tiles_x, tiles_y);
+                           lz, tiles_x, tiles_y, (unsigned long long)step_next, c->has_boundary ? 1 : 0);
         break;
     default:
         hipLaunchKernelGGL(k_step_fused<ST_BF16>, dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in, out,
-                           lz, tiles_x, tiles_y);
+                           lz, tiles_x, tiles_y, (unsigned long long)step_next, c->has_boundary ? 1 : 0);
         break;
     }
     return hipGetLastError();

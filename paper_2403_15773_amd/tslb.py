@@ -27,7 +27,7 @@ EXPORTS = [
     "tslb_params_init", "tslb_params_size", "tslb_required_bytes", "tslb_create", "tslb_set_state", "tslb_step", "tslb_sync",
     "tslb_moments", "tslb_phase", "tslb_state_bytes", "tslb_get_state_raw", "tslb_set_state_raw",
     "tslb_diagnostics", "tslb_step_index", "tslb_set_timing", "tslb_last_step_kernel_ms", "tslb_set_kernel",
-    "tslb_destroy", "tslb_last_error",
+    "tslb_copy_bandwidth", "tslb_destroy", "tslb_last_error",
 ]
 KERNEL_FUSED, KERNEL_GATHER = 0, 1
 
@@ -91,6 +91,8 @@ def load_library(path: str = LIB_PATH):
             "tslb_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
             "tslb_last_step_kernel_ms": (ctypes.c_double, [vp]),
             "tslb_set_kernel": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
+            "tslb_copy_bandwidth": (ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, ctypes.c_int,
+                                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
             "tslb_destroy": (None, [vp]),
             "tslb_last_error": (ctypes.c_char_p, [vp]),
         }
@@ -122,6 +124,16 @@ def make_params(nx, ny, nz, nu, sigma=0.0, width=3.0, gamma=0.0, eps=-1.0, bc=(0
     p.device_buffer_bytes = int(device_buffer_bytes)
     p.stream = stream
     return p
+
+
+def copy_bandwidth(nbytes: int, iters: int = 20, device: int = 0):
+    """(GB/s of read + written bytes, median ms) of the library's plain copy kernel."""
+    lib = load_library()
+    g, m = ctypes.c_double(), ctypes.c_double()
+    rc = lib.tslb_copy_bandwidth(int(device), int(nbytes), int(iters), ctypes.byref(g), ctypes.byref(m))
+    if rc != OK:
+        raise TslbError(rc, lib.tslb_last_error(None).decode())
+    return g.value, m.value
 
 
 def required_bytes(params: Params) -> int:
