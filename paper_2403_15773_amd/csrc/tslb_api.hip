@@ -136,6 +136,11 @@ int tslb_create(const tslb_params *p, tslb_ctx **out) {
     if (!c) return fail(nullptr, TSLB_E_NOMEM, "host allocation failed");
     c->p = *p;
     c->storage = p->storage;
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
+            c->cu_count = cus;
+    }
     Geo &g = c->geo;
     g.nx = p->nx; g.ny = p->ny; g.nz = p->nz;
     for (int a = 0; a < 3; ++a) g.per[a] = p->bc[2 * a] == TSLB_BC_PERIODIC;
@@ -371,7 +376,7 @@ int tslb_set_kernel(tslb_ctx *c, int kernel, int chunk_z) {
     if (kernel != TSLB_KERNEL_FUSED && kernel != TSLB_KERNEL_GATHER) return fail(c, TSLB_E_INVAL, "unknown kernel");
     if (chunk_z < 0) return fail(c, TSLB_E_INVAL, "chunk_z must be >= 0");
     c->kernel = kernel;
-    if (chunk_z > 0) c->chunk_z = chunk_z;
+    c->chunk_z = chunk_z;
     return TSLB_OK;
 }
 

@@ -154,7 +154,10 @@ __device__ __forceinline__ int boundary_face(const Geo &g, int x, int y, int z) 
 __device__ __forceinline__ void apply_boundary_rule(const Phys &ph, const Geo &g, int face, int x, int y,
                                                     unsigned long long step, float m[10], int32_t &phi) {
     const int axis = face >> 1;
-    switch (ph.bc[face]) {
+    // constant indices keep the rule table in scalar registers
+    const int rule = face == 0 ? ph.bc[0] : face == 1 ? ph.bc[1] : face == 2 ? ph.bc[2]
+                   : face == 3 ? ph.bc[3] : face == 4 ? ph.bc[4] : ph.bc[5];
+    switch (rule) {
     case 1:  // free slip: no normal velocity, no normal-tangential stress
         m[1 + axis] = 0.f;
         if (axis == 0) { m[7] = 0.f; m[8] = 0.f; }

@@ -57,7 +57,8 @@ struct tslb_ctx {
     tslb::Scratch scratch;
     tslb::StepTimer timer;
     int kernel = TSLB_KERNEL_FUSED;  // step kernel selected by tslb_set_kernel
-    int chunk_z = 32;                // z planes per workgroup of the fused kernel
+    int chunk_z = 0;                 // z planes per workgroup of the fused kernel (0: automatic)
+    int cu_count = 256;              // compute units of the device
     std::string err;
 };
 
@@ -74,6 +75,7 @@ hipError_t launch_boundary(const tslb_ctx *c, StateView st, int64_t step, hipStr
 hipError_t launch_step(const tslb_ctx *c, StateView in, StateView out, int64_t step_next, hipStream_t s);
 hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int lz, int64_t step_next,
                              hipStream_t s);
+int fused_chunk(const tslb_ctx *c);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
 hipError_t launch_diagnostics(const tslb_ctx *c, StateView st, const Scratch &sc, hipStream_t s);
 size_t diagnostics_blocks(const tslb_ctx *c);

@@ -486,7 +486,7 @@ hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream
 // materialised interface geometry of `in` followed by the gather update of the
 // interior (the caller fills the boundary layers separately).
 hipError_t launch_step(const tslb_ctx *c, StateView in, StateView out, int64_t step_next, hipStream_t s) {
-    if (c->kernel == TSLB_KERNEL_FUSED) return launch_step_fused(c, in, out, c->chunk_z, step_next, s);
+    if (c->kernel == TSLB_KERNEL_FUSED) return launch_step_fused(c, in, out, fused_chunk(c), step_next, s);
     hipError_t e = launch_geometry(c, in.phi, c->scratch.geo, s);
     if (e != hipSuccess) return e;
     return launch_step_gather(c, in, c->scratch.geo, out, s);

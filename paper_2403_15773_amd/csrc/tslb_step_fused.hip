@@ -33,6 +33,8 @@
 // tau_i + (rho'(source) - rho'(own column)), exact differences of neighbours, and
 // puts rho'(own column) back into the zeroth moment only.  No sum is rounded at
 // the magnitude of rho' except the final density itself.
+#include <algorithm>
+
 #include "tslb_internal.h"
 
 namespace tslb {
@@ -542,6 +544,18 @@ __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, St
 }
 
 }  // namespace fused
+
+// z planes per workgroup: the fixed choice of tslb_set_kernel, else the longest
+// chunk (at most 64 planes) that still gives every compute unit a workgroup.
+// Each chunk re-reads 6 planes of halo, so long chunks waste less.
+int fused_chunk(const tslb_ctx *c) {
+    using namespace fused;
+    if (c->chunk_z > 0) return c->chunk_z;
+    const long long tiles = (long long)((c->geo.nx + TX - 1) / TX) * ((c->geo.ny + TY - 1) / TY);
+    const long long chunks = (c->cu_count + tiles - 1) / tiles;
+    const long long lz = (c->geo.nz + chunks - 1) / chunks;
+    return (int)std::max(4LL, std::min(64LL, lz));
+}
 
 // Launch the fused step over the whole lattice.
 hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int lz, int64_t step_next,
