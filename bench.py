@@ -1,18 +1,25 @@
 """Throughput of the multicomponent TSLB step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload jet128] [--storage fp32]
+                    [--variants fp16,bf16] [--serve 256] [--cpu-seconds 15]
 
-One step = the boundary-layer fill plus the fused pull-stream-collide step over
-the whole lattice (every row of the hot path).  The state is resident in HBM
-before the timed region.  Prints one JSON line with GLUPS (n_x n_y n_z n_steps
-/ (1e9 T)), the roofline of the dominant kernel (the fused step: algorithmic
-bytes = the state read once and written once, 88 B/node in binary32 and 48 B/node
-with 16-bit moments) measured with HIP events on the library's stream, and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+One step = the fused pull-stream-collide step over the whole lattice, which also
+writes the boundary layers of the state it produces (every row of the hot path).
+The state is resident in HBM before the timed region.  Prints one JSON line:
+  value / roofline  GLUPS (n_x n_y n_z n_steps / (1e9 T)) of the main run and the
+                    roofline of its dominant kernel (the fused step; algorithmic
+                    bytes = the state read once and written once: 88 B/node in
+                    binary32, 48 B/node with 16-bit moments), the kernel time
+                    measured with HIP events on the library's stream;
+  storage_variants  the same workload with FP16/BF16-stored moments;
+  serving           the seeded request stream run by continuous batching
+                    (p50/p99 latency, aggregate GLUPS);
+  cpu_baseline      the FP64 CPU oracle timed on a bounded sample of the workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,6 +30,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 BYTES_PER_NODE = {"fp32": 88, "fp16": 48, "bf16": 48}
+# HBM traffic of the fused step from rocprofv3 counters, valid while the kernel
+# sources hash to the value recorded next to the figures
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_step_jet128_traffic.txt")
+KERNEL_SOURCES = ["paper_2403_15773_amd/csrc/tslb_step_fused.hip", "paper_2403_15773_amd/csrc/tslb_device.h"]
 
 
 def parse():
@@ -32,21 +43,26 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="jet128", choices=["jet128", "jet512", "droplet32"])
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--variants", default="fp16,bf16", help="other storage types timed on the same workload")
+    ap.add_argument("--serve", type=int, default=256, help="requests in the serving stream (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-oracle sample budget (0 = skip)")
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the copy-kernel ceiling probe (0 = skip)")
     ap.add_argument("--kernel", default="fused", choices=["fused", "gather"])
     return ap.parse_args()
 
 
+def log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def workload_state(name):
+    """(parameters, physical initial fields or None for a quiescent start)."""
     from paper_2403_15773_amd import inputs
     w = inputs.WORKLOADS[name]
     p = w["params"]
     if w["init"] == "droplet":
-        st = inputs.droplet(p["nx"], 8.0, p["width"], noise_amp=1e-3, seed=1)
-    else:
-        st = inputs.quiescent(p["nx"], p["ny"], p["nz"])
-    return p, st
+        return p, inputs.droplet(p["nx"], 8.0, p["width"], noise_amp=1e-3, seed=1)
+    return p, None
 
 
 def describe(name, p):
@@ -60,7 +76,91 @@ def describe(name, p):
             "nodes": p["nx"] * p["ny"] * p["nz"]}
 
 
-def cpu_baseline(name, p, st, budget_s):
+def sources_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, storage):
+    """HBM bytes per fused-step launch from the committed counter summary, or
+    None when it covers another workload or the kernel changed since."""
+    if workload != "jet128" or storage != "fp32" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_sources_sha256") != sources_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_lattice(name, storage, steps, warmup, kernel="fused"):
+    """Time `steps` steps of workload `name`; returns the measurements."""
+    import numpy as np
+
+    from paper_2403_15773_amd.tslb import Simulation
+    p, st = workload_state(name)
+    nodes = p["nx"] * p["ny"] * p["nz"]
+    sim = Simulation(**p, eps=1e-4, storage=storage, u_scale=0.05, device=0)
+    sim.set_kernel(kernel)
+    if st is None:
+        # quiescent: rho = 1, u = 0, P = 0, phi = 0 is the all-zero raw state
+        sim.set_state_raw(np.zeros(sim.state_bytes, np.uint8), step=0)
+    else:
+        sim.set_state(rho_dev=np.asarray(st["rho"] - 1.0, np.float32), u=np.asarray(st["u"], np.float32),
+                      P=np.asarray(st["P"], np.float32), phi=np.asarray(st["phi"], np.float32))
+    log("%s %s, warmup %d" % (name, storage, warmup))
+    sim.step(warmup)
+    sim.sync()
+    sim.set_timing(True)
+    sim.sync()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    t1 = time.perf_counter()
+    kernel_ms = sim.last_step_kernel_ms()
+    diag = sim.diagnostics()
+    sim.close()
+    T = t1 - t0
+    bpn = BYTES_PER_NODE[storage]
+    achieved = bpn * nodes / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else None
+    log("%s %s: %.3f s for %d steps, kernel %.4f ms/launch, finite=%s" % (name, storage, T, steps, kernel_ms,
+                                                                          diag["finite"]))
+    return {"p": p, "st": st, "nodes": nodes, "T": T, "glups": nodes * steps / T / 1e9, "kernel_ms": kernel_ms,
+            "achieved": achieved, "bpn": bpn, "finite": diag["finite"]}
+
+
+def serving(n_requests):
+    """The seeded request stream (Poisson arrivals at 20/s, boxes 32..128,
+    droplet/jet, Re 500..5000, We 10..2000, 500..5000 steps) through the
+    serving group."""
+    from paper_2403_15773_amd import serve
+    from paper_2403_15773_amd.tslb import Group
+    reqs = serve.make_requests(n_requests, rate=20.0, master_seed=5)
+    budget = 64 << 30
+    log("serving %d requests" % n_requests)
+    t0 = time.perf_counter()
+    with Group(hbm_budget_bytes=budget, max_domains=64) as g:
+        recs = serve.serve(reqs, serve.GpuBackend(g), budget, max_domains=64)
+    s = serve.summarise(recs)
+    log("serving: p50 %.2f s, p99 %.2f s, %.2f GLUPS aggregate, %d unstable, %.1f s wall" % (
+        s["p50_latency_s"], s["p99_latency_s"], s["aggregate_glups"], s["unstable"], time.perf_counter() - t0))
+    s["stream"] = ("%d requests, Poisson arrivals 20/s (master seed 5), cubic L in {32,48,64,96,128}, droplet/jet "
+                   "50/50, Re log-U[500,5000], We log-U[10,2000], steps U{500..5000}, FP32, budget 64 GiB, "
+                   "64 domain slots" % n_requests)
+    return s
+
+
+def cpu_baseline(p, st, budget_s):
     """The FP64 oracle as it stands, on this host's cores, for a bounded number of
     steps of the same workload; rate in GLUPS."""
     if budget_s <= 0:
@@ -72,6 +172,9 @@ def cpu_baseline(name, p, st, budget_s):
     o = Oracle(p["nx"], p["ny"], p["nz"], nu=p["nu"], sigma=p["sigma"], width=p["width"], eps=1e-4, bc=p["bc"],
                inlet_u=p.get("inlet_u", 0.0), inlet_d=p.get("inlet_d", 0.0), inlet_noise=p.get("inlet_noise", 0.0),
                seed=p.get("seed", 0))
+    if st is None:
+        from paper_2403_15773_amd import inputs
+        st = inputs.quiescent(p["nx"], p["ny"], p["nz"])
     o.set_physical(**{k: np.asarray(v, np.float64) for k, v in st.items()})
     t0 = time.perf_counter()
     o.step(1)
@@ -92,60 +195,45 @@ def main():
     if a.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % a.gpus, file=sys.stderr)
         sys.exit(2)
-    from paper_2403_15773_amd.tslb import Simulation
-    import numpy as np
-
-    p, st = workload_state(a.workload)
-    nodes = p["nx"] * p["ny"] * p["nz"]
     from paper_2403_15773_amd.tslb import copy_bandwidth
+
     copy = None
     if a.copy_mib > 0:
         gbps, cms = copy_bandwidth(a.copy_mib << 20, iters=20)
         copy = {"gbps": gbps, "ms": cms, "bytes_moved": 2 * (a.copy_mib << 20)}
-        print("bench: copy-kernel ceiling %.0f GB/s (%d MiB read + written, %.3f ms)" % (gbps, 2 * a.copy_mib, cms),
-              file=sys.stderr, flush=True)
-    sim = Simulation(**p, eps=1e-4, storage=a.storage, device=0)
-    sim.set_kernel(a.kernel)
-    sim.set_state(rho_dev=np.asarray(st["rho"] - 1.0, np.float32), u=np.asarray(st["u"], np.float32),
-                  P=np.asarray(st["P"], np.float32), phi=np.asarray(st["phi"], np.float32))
-    print("bench: %s %s, warmup %d" % (a.workload, a.storage, a.warmup), file=sys.stderr, flush=True)
-    sim.step(a.warmup)
-    sim.sync()
-    sim.set_timing(True)
-    sim.sync()
-    t0 = time.perf_counter()
-    sim.step(a.steps)
-    sim.sync()
-    t1 = time.perf_counter()
-    kernel_ms = sim.last_step_kernel_ms()
-    diag = sim.diagnostics()
-    sim.close()
-    T = t1 - t0
-    glups = nodes * a.steps / T / 1e9
-    bpn = BYTES_PER_NODE[a.storage]
-    achieved = bpn * nodes / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else None
-    print("bench: %.3f s for %d steps, kernel %.4f ms/launch, finite=%s" % (T, a.steps, kernel_ms, diag["finite"]),
-          file=sys.stderr, flush=True)
+        log("copy-kernel ceiling %.0f GB/s (%d MiB read + written, %.3f ms)" % (gbps, 2 * a.copy_mib, cms))
+    m = run_lattice(a.workload, a.storage, a.steps, a.warmup, a.kernel)
+    p, nodes, achieved = m["p"], m["nodes"], m["achieved"]
+    traffic = measured_traffic(a.workload, a.storage) if a.kernel == "fused" else None
+    variants = {}
+    for v in [s for s in a.variants.split(",") if s and s != a.storage]:
+        r = run_lattice(a.workload, v, max(1, a.steps // 2), max(1, a.warmup // 2), a.kernel)
+        variants[v] = {"value": r["glups"], "unit": "GLUPS", "kernel_ms": r["kernel_ms"],
+                       "roofline_frac": r["achieved"] / HBM_PEAK_GBS if r["achieved"] else None,
+                       "bytes_per_node": r["bpn"], "speedup_vs_%s" % a.storage: r["glups"] / m["glups"],
+                       "finite": r["finite"]}
     rec = {
         "metric": "GLUPS (lattice-node updates per second / 1e9) and fraction of the HBM roofline",
-        "value": glups,
+        "value": m["glups"],
         "unit": "GLUPS",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": T / a.steps * 1e3,
+        "ms_per_step": m["T"] / a.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if a.storage == "fp32" else "f32 (%s-stored moments)" % a.storage,
         "data": "synthetic",
-        "config": describe(a.workload, p) | {"storage": a.storage, "finite": diag["finite"]},
+        "config": describe(a.workload, p) | {"storage": a.storage, "finite": m["finite"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
-                     "kernel": "%s step" % a.kernel, "bytes_per_node": bpn, "kernel_ms": kernel_ms,
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
+                     "kernel": "%s step" % a.kernel, "bytes_per_node": m["bpn"], "kernel_ms": m["kernel_ms"],
                      "copy_ceiling": copy["gbps"] if copy else None,
                      "frac_of_copy_ceiling": achieved / copy["gbps"] if (copy and achieved) else None},
-        "cpu_baseline": cpu_baseline(a.workload, p, st, a.cpu_seconds),
+        "storage_variants": variants,
+        "serving": serving(a.serve) if a.serve > 0 else None,
+        "cpu_baseline": cpu_baseline(p, m["st"], a.cpu_seconds),
     }
     print(json.dumps(rec), flush=True)
 

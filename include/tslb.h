@@ -173,11 +173,62 @@ int tslb_set_kernel(tslb_ctx *ctx, int kernel, int chunk_z);
  * ceiling and as the reference for scaling hardware byte counters. */
 int tslb_copy_bandwidth(int device, size_t bytes, int iters, double *gbps, double *ms);
 
-/* Release the context and everything it allocated. */
+/* Release the context and everything it allocated.  A member of a serving
+ * group is first removed from it (after the group's queued work). */
 void tslb_destroy(tslb_ctx *ctx);
 
 /* Text of the last error of ctx, or of the calling thread when ctx is NULL. */
 const char *tslb_last_error(const tslb_ctx *ctx);
+
+/* ---- Serving: continuous batching of many lattices ------------------------
+ *
+ * A group advances several contexts (lattices of different sizes and
+ * parameters, the mixed request stream of a solver service) together: every
+ * tslb_group_poll() launches ONE fused step kernel that updates every member
+ * with steps left (one launch per storage type present), so requests that
+ * arrive while others run share the device from their first step on.  A
+ * member's update reads and writes only its own lattice (the step of the
+ * method has no cross-node reduction), so its result is bitwise the one it
+ * gets when run alone.  Admission is by HBM budget and slot count; members
+ * join and leave between steps.
+ *
+ * While a context is a member, the group owns it: every tslb_* call on it
+ * except tslb_destroy returns TSLB_E_STATE until a poll has retired it.
+ * Groups use the fused kernel only; diagnostics (tslb_diagnostics) are the
+ * caller's, after retirement. */
+typedef struct tslb_group tslb_group;
+
+/* Create a group on the current HIP device.  hbm_budget_bytes caps the summed
+ * state bytes (two buffers per member) of the members; max_domains (1..4096)
+ * caps their count; stream is a hipStream_t for the group's launches, or NULL
+ * for one the group creates.  Errors: TSLB_E_INVAL, TSLB_E_NOMEM,
+ * TSLB_E_DEVICE (text from tslb_last_error(NULL)). */
+int tslb_group_create(size_t hbm_budget_bytes, int32_t max_domains, void *stream, tslb_group **out);
+
+/* Admit ctx (state set, fused kernel, same device) to run nsteps more steps.
+ * The group's launches start after the work already queued on ctx's stream.
+ * Returns TSLB_E_NOMEM when the budget or the slots would be exceeded: the
+ * caller defers the request and retries after a poll has retired members.
+ * nsteps may be 0 (the member is retired by the next poll). */
+int tslb_group_admit(tslb_group *g, tslb_ctx *ctx, int64_t nsteps);
+
+/* Retire finished members and launch the next step of the others.  A member is
+ * retired once the device has finished its last step; up to cap retired
+ * contexts are written to done[] (admission order) and counted in *ndone.
+ * Retired contexts are the caller's again, at step index start + nsteps.  At
+ * most 4 steps are in flight: a poll may wait for the oldest. */
+int tslb_group_poll(tslb_group *g, tslb_ctx **done, int32_t cap, int32_t *ndone);
+
+/* Bytes charged to the budget, number of members and launches so far (each
+ * pointer may be NULL). */
+int tslb_group_status(const tslb_group *g, size_t *bytes_in_use, int32_t *members, int64_t *launches);
+
+/* Wait for the group's work and release it; members become free contexts at
+ * the step their last launched update reached. */
+void tslb_group_destroy(tslb_group *g);
+
+/* Text of the last error of g, or of the calling thread when g is NULL. */
+const char *tslb_group_last_error(const tslb_group *g);
 
 #ifdef __cplusplus
 }

@@ -100,6 +100,17 @@ int run_diagnostics(tslb_ctx *c, double out[2], long long *phi_fixed) {
 
 }  // namespace
 
+namespace tslb {
+void set_thread_error(const std::string &msg) { g_thread_error = msg; }
+}  // namespace tslb
+
+// A context that is a member of a serving group is advanced by the group; every
+// call that reads or writes its state waits until the group has retired it.
+#define NOT_IN_GROUP(c)                                                                                  \
+    do {                                                                                                 \
+        if ((c)->group) return fail((c), TSLB_E_STATE, "ctx is a member of a serving group");           \
+    } while (0)
+
 extern "C" {
 
 void tslb_params_init(tslb_params *p) {
@@ -221,6 +232,7 @@ int tslb_create(const tslb_params *p, tslb_ctx **out) {
 int tslb_set_state(tslb_ctx *c, const float *rho_dev, const float *u, const float *pi_neq, const float *phi,
                    int64_t step) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    NOT_IN_GROUP(c);
     if (!rho_dev || !u || !pi_neq || !phi) return fail(c, TSLB_E_INVAL, "every field is required");
     if (step < 0) return fail(c, TSLB_E_INVAL, "step must be >= 0");
     int rc = ensure_planes(c);
@@ -240,6 +252,7 @@ int tslb_set_state(tslb_ctx *c, const float *rho_dev, const float *u, const floa
 
 int tslb_step(tslb_ctx *c, int64_t nsteps) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    NOT_IN_GROUP(c);
     if (nsteps < 0) return fail(c, TSLB_E_INVAL, "nsteps must be >= 0");
     if (!c->state_set) return fail(c, TSLB_E_STATE, "no state: call tslb_set_state first");
     int rc = c->kernel == TSLB_KERNEL_GATHER ? ensure_planes(c) : TSLB_OK;
@@ -292,12 +305,14 @@ int tslb_step(tslb_ctx *c, int64_t nsteps) {
 
 int tslb_sync(tslb_ctx *c) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    NOT_IN_GROUP(c);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return TSLB_OK;
 }
 
 int tslb_moments(tslb_ctx *c, float *rho_dev, float *u, float *pi_neq) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    NOT_IN_GROUP(c);
     if (!c->state_set) return fail(c, TSLB_E_STATE, "no state");
     int rc = ensure_planes(c);
     if (rc) return rc;
@@ -317,6 +332,7 @@ int tslb_moments(tslb_ctx *c, float *rho_dev, float *u, float *pi_neq) {
 
 int tslb_phase(tslb_ctx *c, float *phi) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    NOT_IN_GROUP(c);
     if (!phi) return fail(c, TSLB_E_INVAL, "phi is NULL");
     if (!c->state_set) return fail(c, TSLB_E_STATE, "no state");
     int rc = fill_boundary_now(c);
@@ -333,6 +349,7 @@ size_t tslb_state_bytes(const tslb_ctx *c) { return c ? c->buffer_bytes : 0; }
 
 int tslb_get_state_raw(tslb_ctx *c, void *host, size_t bytes) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    NOT_IN_GROUP(c);
     if (!host || bytes != c->buffer_bytes) return fail(c, TSLB_E_INVAL, "bytes must equal tslb_state_bytes()");
     if (!c->state_set) return fail(c, TSLB_E_STATE, "no state");
     int rc = fill_boundary_now(c);
@@ -344,6 +361,7 @@ int tslb_get_state_raw(tslb_ctx *c, void *host, size_t bytes) {
 
 int tslb_set_state_raw(tslb_ctx *c, const void *host, size_t bytes, int64_t step) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    NOT_IN_GROUP(c);
     if (!host || bytes != c->buffer_bytes) return fail(c, TSLB_E_INVAL, "bytes must equal tslb_state_bytes()");
     if (step < 0) return fail(c, TSLB_E_INVAL, "step must be >= 0");
     HIP_TRY(c, hipMemcpyAsync(c->buf[c->cur].mom, host, bytes, hipMemcpyHostToDevice, c->stream));
@@ -355,6 +373,7 @@ int tslb_set_state_raw(tslb_ctx *c, const void *host, size_t bytes, int64_t step
 
 int tslb_diagnostics(tslb_ctx *c, double *mass, double *phase_sum, int64_t *step, int32_t *finite) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    NOT_IN_GROUP(c);
     if (!c->state_set) return fail(c, TSLB_E_STATE, "no state");
     int rc = fill_boundary_now(c);
     if (rc) return rc;
@@ -373,6 +392,7 @@ int64_t tslb_step_index(const tslb_ctx *c) { return c ? c->step : -1; }
 
 int tslb_set_kernel(tslb_ctx *c, int kernel, int chunk_z) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    NOT_IN_GROUP(c);
     if (kernel != TSLB_KERNEL_FUSED && kernel != TSLB_KERNEL_GATHER) return fail(c, TSLB_E_INVAL, "unknown kernel");
     if (chunk_z < 0) return fail(c, TSLB_E_INVAL, "chunk_z must be >= 0");
     c->kernel = kernel;
@@ -442,6 +462,7 @@ int tslb_copy_bandwidth(int device, size_t bytes, int iters, double *gbps, doubl
 
 void tslb_destroy(tslb_ctx *c) {
     if (!c) return;
+    if (c->group) group_detach(c->group, c);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (hipEvent_t ev : c->timer.ev) (void)hipEventDestroy(ev);
     if (c->scratch.stage) (void)hipFree(c->scratch.stage);

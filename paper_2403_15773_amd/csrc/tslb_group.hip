@@ -1,0 +1,251 @@
+// Serving: a group of lattices advanced together by one multi-domain fused
+// step launch (continuous batching at step granularity).  Declarations and
+// contracts are in include/tslb.h.
+//
+// Each tslb_group_poll() call retires the members whose last step has finished
+// on the device and launches one step of every member with steps left.  A
+// launch reads a device table of FusedDomain records (one per member, grouped
+// by storage type); the tables live in a ring of kRing slots so that up to
+// kRing launches are in flight, and a slot's pinned host copy is rewritten only
+// after the event of the launch that last used it has completed.
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "tslb_internal.h"
+
+using namespace tslb;
+
+struct tslb_group {
+    static constexpr int kRing = 4;
+    size_t budget = 0;
+    int max_domains = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool owns_stream = false;
+    size_t bytes_in_use = 0;
+    struct Member {
+        tslb_ctx *ctx;
+        int64_t remaining;    // steps still to launch
+        int64_t last_launch;  // launch that wrote its newest state (-1: none)
+        size_t bytes;         // HBM charged against the budget
+    };
+    std::vector<Member> members;  // in admission order
+    FusedDomain *h_tab[kRing] = {};
+    FusedDomain *d_tab[kRing] = {};
+    hipEvent_t ev[kRing] = {};
+    int64_t slot_launch[kRing] = {-1, -1, -1, -1};
+    int64_t launches = 0;        // launches issued
+    int64_t completed = -1;      // every launch <= completed has finished
+    hipEvent_t admit_ev = nullptr;
+    std::string err;
+};
+
+namespace {
+
+int gfail(tslb_group *g, int code, const std::string &msg) {
+    if (g)
+        g->err = msg;
+    else
+        set_thread_error(msg);
+    return code;
+}
+
+#define GHIP_TRY(g, expr)                                                                                 \
+    do {                                                                                                  \
+        hipError_t e_ = (expr);                                                                           \
+        if (e_ != hipSuccess)                                                                             \
+            return gfail((g), TSLB_E_DEVICE, std::string(#expr) + " failed: " + hipGetErrorString(e_));   \
+    } while (0)
+
+// Advance g->completed over the launches whose slot events have fired.
+int refresh_completed(tslb_group *g) {
+    while (g->completed + 1 < g->launches) {
+        const int64_t next = g->completed + 1;
+        const int slot = (int)(next % tslb_group::kRing);
+        const hipError_t q = hipEventQuery(g->ev[slot]);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) return gfail(g, TSLB_E_DEVICE, std::string("hipEventQuery: ") + hipGetErrorString(q));
+        g->completed = next;
+    }
+    return TSLB_OK;
+}
+
+void release_all(tslb_group *g) {
+    for (int s = 0; s < tslb_group::kRing; ++s) {
+        if (g->ev[s]) (void)hipEventDestroy(g->ev[s]);
+        if (g->d_tab[s]) (void)hipFree(g->d_tab[s]);
+        if (g->h_tab[s]) (void)hipHostFree(g->h_tab[s]);
+    }
+    if (g->admit_ev) (void)hipEventDestroy(g->admit_ev);
+    if (g->owns_stream && g->stream) (void)hipStreamDestroy(g->stream);
+}
+
+}  // namespace
+
+namespace tslb {
+
+// Remove ctx from its group (tslb_destroy of a member): wait for the group's
+// work, then forget the member and return its bytes to the budget.
+void group_detach(tslb_group *g, tslb_ctx *c) {
+    if (!g || !c) return;
+    (void)hipStreamSynchronize(g->stream);
+    for (size_t i = 0; i < g->members.size(); ++i)
+        if (g->members[i].ctx == c) {
+            g->bytes_in_use -= g->members[i].bytes;
+            g->members.erase(g->members.begin() + (long)i);
+            break;
+        }
+    c->group = nullptr;
+}
+
+}  // namespace tslb
+
+extern "C" {
+
+int tslb_group_create(size_t hbm_budget_bytes, int32_t max_domains, void *stream, tslb_group **out) {
+    if (!out) return gfail(nullptr, TSLB_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (max_domains < 1 || max_domains > 4096) return gfail(nullptr, TSLB_E_INVAL, "max_domains must be in [1, 4096]");
+    if (hbm_budget_bytes == 0) return gfail(nullptr, TSLB_E_INVAL, "hbm_budget_bytes must be positive");
+    tslb_group *g = new (std::nothrow) tslb_group();
+    if (!g) return gfail(nullptr, TSLB_E_NOMEM, "host allocation failed");
+    g->budget = hbm_budget_bytes;
+    g->max_domains = max_domains;
+    hipError_t e = hipGetDevice(&g->device);
+    // three storage types share one table of 3 * max_domains records per slot
+    const size_t tab = 3 * (size_t)max_domains * sizeof(FusedDomain);
+    for (int s = 0; e == hipSuccess && s < tslb_group::kRing; ++s) {
+        e = hipHostMalloc((void **)&g->h_tab[s], tab, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc((void **)&g->d_tab[s], tab);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&g->ev[s], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&g->admit_ev, hipEventDisableTiming);
+    if (e == hipSuccess) {
+        if (stream) {
+            g->stream = (hipStream_t)stream;
+        } else {
+            e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
+            g->owns_stream = e == hipSuccess;
+        }
+    }
+    if (e != hipSuccess) {
+        const int code = e == hipErrorOutOfMemory ? TSLB_E_NOMEM : TSLB_E_DEVICE;
+        release_all(g);
+        delete g;
+        return gfail(nullptr, code, std::string("group set-up failed: ") + hipGetErrorString(e));
+    }
+    *out = g;
+    return TSLB_OK;
+}
+
+int tslb_group_admit(tslb_group *g, tslb_ctx *c, int64_t nsteps) {
+    if (!g) return gfail(nullptr, TSLB_E_INVAL, "group is NULL");
+    if (!c) return gfail(g, TSLB_E_INVAL, "ctx is NULL");
+    if (nsteps < 0) return gfail(g, TSLB_E_INVAL, "nsteps must be >= 0");
+    if (c->group) return gfail(g, TSLB_E_STATE, "ctx is already in a group");
+    if (!c->state_set) return gfail(g, TSLB_E_STATE, "ctx has no state");
+    if (c->kernel != TSLB_KERNEL_FUSED) return gfail(g, TSLB_E_STATE, "groups run the fused step kernel only");
+    if (c->p.device != g->device) return gfail(g, TSLB_E_INVAL, "ctx and group are on different devices");
+    if ((int)g->members.size() >= g->max_domains) return gfail(g, TSLB_E_NOMEM, "all domain slots are taken");
+    const size_t bytes = 2 * c->buffer_bytes;
+    if (g->bytes_in_use + bytes > g->budget) return gfail(g, TSLB_E_NOMEM, "HBM budget exhausted");
+    // the group stream starts after everything already queued on the ctx
+    GHIP_TRY(g, hipEventRecord(g->admit_ev, c->stream));
+    GHIP_TRY(g, hipStreamWaitEvent(g->stream, g->admit_ev, 0));
+    // the fused step writes the boundary layers of the states it produces; the
+    // current state's layers are filled once here (the fill is idempotent)
+    if (nsteps > 0) GHIP_TRY(g, launch_boundary(c, c->buf[c->cur], c->step, g->stream));
+    // a member with no steps is done once the work queued so far has finished
+    g->members.push_back({c, nsteps, nsteps > 0 ? -1 : g->launches - 1, bytes});
+    g->bytes_in_use += bytes;
+    c->group = g;
+    return TSLB_OK;
+}
+
+int tslb_group_poll(tslb_group *g, tslb_ctx **done, int32_t cap, int32_t *ndone) {
+    if (!g) return gfail(nullptr, TSLB_E_INVAL, "group is NULL");
+    if (!ndone) return gfail(g, TSLB_E_INVAL, "ndone is NULL");
+    if (cap < 0 || (cap > 0 && !done)) return gfail(g, TSLB_E_INVAL, "done/cap invalid");
+    *ndone = 0;
+    int rc = refresh_completed(g);
+    if (rc) return rc;
+    // retire members whose newest state is complete (admission order)
+    for (size_t i = 0; i < g->members.size() && *ndone < cap;) {
+        tslb_group::Member &m = g->members[i];
+        if (m.remaining == 0 && m.last_launch <= g->completed) {
+            if (m.last_launch < 0) {  // no launch at all: wait for its boundary fill
+                const hipError_t q = hipStreamQuery(g->stream);
+                if (q == hipErrorNotReady) { ++i; continue; }
+                if (q != hipSuccess) return gfail(g, TSLB_E_DEVICE, std::string("hipStreamQuery: ") + hipGetErrorString(q));
+            }
+            done[(*ndone)++] = m.ctx;
+            m.ctx->group = nullptr;
+            g->bytes_in_use -= m.bytes;
+            g->members.erase(g->members.begin() + (long)i);
+        } else {
+            ++i;
+        }
+    }
+    // one step of every member with steps left
+    bool any = false;
+    for (const tslb_group::Member &m : g->members) any = any || m.remaining > 0;
+    if (!any) return TSLB_OK;
+    const int64_t id = g->launches;
+    const int slot = (int)(id % tslb_group::kRing);
+    if (g->slot_launch[slot] >= 0 && g->slot_launch[slot] > g->completed) {
+        GHIP_TRY(g, hipEventSynchronize(g->ev[slot]));
+        rc = refresh_completed(g);
+        if (rc) return rc;
+    }
+    FusedDomain *h = g->h_tab[slot];
+    int nrec = 0;
+    int first[3] = {0, 0, 0}, count[3] = {0, 0, 0}, work[3] = {0, 0, 0};
+    for (int st = 0; st < 3; ++st) {
+        first[st] = nrec;
+        for (tslb_group::Member &m : g->members) {
+            tslb_ctx *c = m.ctx;
+            if (m.remaining <= 0 || c->storage != st) continue;
+            h[nrec] = fused_domain(c, c->buf[c->cur], c->buf[c->cur ^ 1], c->step + 1, work[st]);
+            work[st] += h[nrec].work_count;
+            ++nrec;
+            ++count[st];
+        }
+    }
+    GHIP_TRY(g, hipMemcpyAsync(g->d_tab[slot], h, (size_t)nrec * sizeof(FusedDomain), hipMemcpyHostToDevice,
+                               g->stream));
+    for (int st = 0; st < 3; ++st)
+        if (count[st]) GHIP_TRY(g, launch_step_fused_multi(g->d_tab[slot] + first[st], count[st], work[st], st, g->stream));
+    GHIP_TRY(g, hipEventRecord(g->ev[slot], g->stream));
+    g->slot_launch[slot] = id;
+    g->launches = id + 1;
+    for (tslb_group::Member &m : g->members) {
+        if (m.remaining <= 0) continue;
+        m.ctx->cur ^= 1;
+        m.ctx->step += 1;
+        m.remaining -= 1;
+        m.last_launch = id;
+    }
+    return TSLB_OK;
+}
+
+int tslb_group_status(const tslb_group *g, size_t *bytes_in_use, int32_t *members, int64_t *launches) {
+    if (!g) return gfail(nullptr, TSLB_E_INVAL, "group is NULL");
+    if (bytes_in_use) *bytes_in_use = g->bytes_in_use;
+    if (members) *members = (int32_t)g->members.size();
+    if (launches) *launches = g->launches;
+    return TSLB_OK;
+}
+
+void tslb_group_destroy(tslb_group *g) {
+    if (!g) return;
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    for (tslb_group::Member &m : g->members) m.ctx->group = nullptr;
+    release_all(g);
+    delete g;
+}
+
+const char *tslb_group_last_error(const tslb_group *g) { return g ? g->err.c_str() : tslb_last_error(nullptr); }
+
+}  // extern "C"

@@ -17,6 +17,17 @@ struct StateView {
     int32_t *phi;   // phase-field plane (fixed point, 30 fractional bits)
 };
 
+// One lattice of a multi-domain fused step launch (device-resident table).
+struct FusedDomain {
+    Geo g;
+    Phys ph;
+    Scales sc;
+    StateView in, out;
+    unsigned long long step_next;  // step index of the state written
+    int lz, tiles_x, tiles_y;      // z chunk and tile grid
+    int work_begin, work_count;    // work items [work_begin, work_begin + work_count)
+};
+
 // Scratch planes (binary32) used off the per-step path: host staging of
 // physical fields and the interface geometry of set/readout.
 struct Scratch {
@@ -59,10 +70,16 @@ struct tslb_ctx {
     int kernel = TSLB_KERNEL_FUSED;  // step kernel selected by tslb_set_kernel
     int chunk_z = 0;                 // z planes per workgroup of the fused kernel (0: automatic)
     int cu_count = 256;              // compute units of the device
+    tslb_group *group = nullptr;     // serving group that currently advances this ctx
     std::string err;
 };
 
 namespace tslb {
+
+// Error text of a failed call that had no context (read by tslb_last_error(NULL)).
+void set_thread_error(const std::string &msg);
+// Remove a member from its group (waits for the group's queued work).
+void group_detach(tslb_group *g, tslb_ctx *c);
 
 size_t plane_elems(long long N);
 size_t state_buffer_bytes(long long N, int storage);
@@ -76,6 +93,11 @@ hipError_t launch_step(const tslb_ctx *c, StateView in, StateView out, int64_t s
 hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int lz, int64_t step_next,
                              hipStream_t s);
 int fused_chunk(const tslb_ctx *c);
+// Describe one step of ctx c (in -> out) as a domain of a multi-domain launch
+// whose work items start at work_begin.
+FusedDomain fused_domain(const tslb_ctx *c, StateView in, StateView out, int64_t step_next, int work_begin);
+// One fused step of every domain of a device table (all of one storage type).
+hipError_t launch_step_fused_multi(const FusedDomain *doms, int ndom, int total_work, int storage, hipStream_t s);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
 hipError_t launch_diagnostics(const tslb_ctx *c, StateView st, const Scratch &sc, hipStream_t s);
 size_t diagnostics_blocks(const tslb_ctx *c);

@@ -53,7 +53,7 @@ static_assert(NPHI <= 2 * NT && NGEO <= 2 * NT, "staging loops assume two items 
 
 struct Smem {
     int32_t phi[4][NPHI];      // fixed-point phase field, ring of 4 planes
-    float n[3][3][NGEO];       // unit normal, ring of 3 planes
+    float n[2][3][NGEO];       // unit normal, ring of 2 planes
     float G[2][3][NSRC];       // gradient on the source region, ring of 2 planes
     float xch[NXCH][NSRC];     // populations crossing columns
 };
@@ -75,6 +75,10 @@ __device__ __forceinline__ Tr3 tr3(float am, float a0, float ap) {
 __device__ __forceinline__ float tr3_m0(float am, float a0, float ap) {
     return fmaf((am - a0) + (ap - a0), 1.0f / 6.0f, a0);
 }
+
+// Weighted three-point sum with the one-dimensional D3Q27 weights:
+// (1/6) m + (2/3) z + (1/6) p.
+__device__ __forceinline__ float w1sum(float m, float z, float p) { return fmaf(z, 2.0f / 3.0f, (m + p) * (1.0f / 6.0f)); }
 
 // Quadratic A + B c + C (c^2 - 1/3) at c = -1, 0, +1.
 __device__ __forceinline__ void quad3(float A, float B, float C, float &vm, float &v0, float &vp) {
@@ -114,22 +118,24 @@ __device__ __forceinline__ void xy_moments(const float t[9], float X[6]) {
     X[4] = tr3_m0(y0.m2, y1.m2, y2.m2);  // 02
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Work item w is assigned so that every XCD receives a contiguous range of w:
+// the tiles of one z chunk then run side by side on one XCD and their
+// overlapping halos are served by that XCD's L2 instead of HBM.
+__device__ __forceinline__ int xcd_work_item(int b, int nb) {
+    const int q8 = nb >> 3, rem8 = nb & 7;
+    const int xcd = b & 7, slot = b >> 3;
+    return (xcd < rem8 ? xcd * (q8 + 1) : rem8 * (q8 + 1) + (xcd - rem8) * q8) + slot;
+}
+
+// One work item (a tile and a z chunk) of one lattice.
 template <int ST>
-__global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, StateView in, StateView out, int lz,
-                                                   int tiles_x, int tiles_y, unsigned long long step_next,
-                                                   int has_bnd) {
-    __shared__ Smem sm;
+__device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &ph, const Scales &sc,
+                                           const StateView &in, const StateView &out, int lz, int tiles_x,
+                                           int tiles_y, unsigned long long step_next, int w) {
     using S = Store<ST>;
     using T = typename S::T;
 
-    // ---- tile and chunk of this workgroup ----
-    // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
-    // L2.  Work item w is assigned so that every XCD receives a contiguous range
-    // of w: the tiles of one z chunk then run side by side on one XCD and their
-    // overlapping halos are served by that XCD's L2 instead of HBM.
-    const int nb = gridDim.x, q8 = nb >> 3, rem8 = nb & 7;
-    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    const int w = (xcd < rem8 ? xcd * (q8 + 1) : rem8 * (q8 + 1) + (xcd - rem8) * q8) + slot;
     const int tile = w % (tiles_x * tiles_y);
     const int chunk = w / (tiles_x * tiles_y);
     // The tile owns columns [xo, xo + TX) x [yo, yo + TY); its origin (x0, y0) is
@@ -186,13 +192,15 @@ __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, St
         const int gy = wrap_or_clamp(y0 - 3 + py, g.ny, g.per[1]);
         col_phi[k] = (long long)gx + (long long)g.nx * gy;
     }
-    // geometry items (<= 2 per thread): centre (gx, gy) in the 36 x 20 region
+    // geometry items (<= 2 per thread): centre (gx, gy) in the 36 x 20 region.
+    // Waves are placed on the four SIMDs round-robin, and waves 8 and 9 (halo
+    // sources) put a third source wave on SIMDs 0 and 1; the NGEO - NT second
+    // items therefore go to waves 2 and 3 (SIMDs 2 and 3).
+    constexpr int kGeoExtraFirst = 128;
+    static_assert(NGEO - NT <= 128, "second geometry items must fit waves 2 and 3");
     int geo_item[2];
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const int i = t + k * NT;
-        geo_item[k] = i < NGEO ? i : -1;
-    }
+    geo_item[0] = t < NGEO ? t : -1;
+    geo_item[1] = (t >= kGeoExtraFirst && t < kGeoExtraFirst + (NGEO - NT)) ? NT + (t - kGeoExtraFirst) : -1;
 
     const float omega1 = 1.0f - ph.omega;
     const float sigma = ph.sigma, gamma = ph.gamma, eps = ph.eps;
@@ -202,6 +210,7 @@ __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, St
 #pragma unroll
     for (int k = 0; k < 6; ++k) XA[k] = XB[k] = XC[k] = 0.f;
     int32_t PA = 0, PC = 0;  // phase partial sums of planes r - 1 and r (column x_F)
+    float cA = 0.f, cB = 0.f, cC = 0.f, eA = 0.f, eB = 0.f, eC = 0.f;  // curvature partial sums (S3a)
 
     // prefetched raw moments of the next source plane (own column)
     float mom[10];
@@ -276,7 +285,7 @@ __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, St
                             if (cz) G2 = fmaf(w * cz, d, G2);
                         }
                 const float inv = 1.0f / (sqrtf(G0 * G0 + G1 * G1 + G2 * G2) + eps);
-                float *n = &sm.n[(it - 2) % 3][0][0];
+                float *n = &sm.n[it & 1][0][0];
                 n[i] = G0 * inv;
                 n[NGEO + i] = G1 * inv;
                 n[2 * NGEO + i] = G2 * inv;
@@ -298,31 +307,38 @@ __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, St
         if (is_src && it >= 3) load_moments(r + 1, mom);
         __syncthreads();
 
+        // ---- S3a: per-column partial sums of the curvature stencil (plane q) ----
+        // With w_i = w1(c_x) w1(c_y) w1(c_z), w1(0) = 2/3, w1(+-1) = 1/6, the stencil
+        // kappa = 3 sum_i w_i c_i . n(x + c_i) factorises into sums over one plane:
+        //   kappa(r) = (1/2) [ sum_cz w1(cz) C(r + cz) + E(r + 1) - E(r - 1) ],
+        //   C = sum_cy w1(cy) (n_x(x+1, y+cy) - n_x(x-1, y+cy))
+        //     + sum_cx w1(cx) (n_y(x+cx, y+1) - n_y(x+cx, y-1)),
+        //   E = sum_{cx,cy} w1(cx) w1(cy) n_z(x+cx, y+cy),
+        // so each source keeps C and E of three planes in registers.
+        if (it >= 2 && is_src) {
+            const float *nq = &sm.n[it & 1][0][0];
+            const float *nyq = nq + NGEO, *nzq = nq + 2 * NGEO;
+            const int c = (sy + 1) * GX + (sx + 1);  // centre in the geometry region
+            const float Cx = w1sum(nq[c - GX + 1] - nq[c - GX - 1], nq[c + 1] - nq[c - 1], nq[c + GX + 1] - nq[c + GX - 1]);
+            const float Cy = w1sum(nyq[c + GX - 1] - nyq[c - GX - 1], nyq[c + GX] - nyq[c - GX],
+                                   nyq[c + GX + 1] - nyq[c - GX + 1]);
+            const float E = w1sum(w1sum(nzq[c - GX - 1], nzq[c - GX], nzq[c - GX + 1]),
+                                  w1sum(nzq[c - 1], nzq[c], nzq[c + 1]),
+                                  w1sum(nzq[c + GX - 1], nzq[c + GX], nzq[c + GX + 1]));
+            cA = cB;
+            cB = cC;
+            cC = Cx + Cy;
+            eA = eB;
+            eB = eC;
+            eC = E;
+        }
+
         if (it >= 4) {
-            // ---- S3: kappa and F at the source (plane r) ----
+            // ---- S3: kappa and F at the source (plane r = q - 1) ----
             float F0 = 0.f, F1 = 0.f, F2 = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
             int32_t phis = 0;
             if (is_src) {
-                const float *nm = &sm.n[(it - 4) % 3][0][0], *n0p = &sm.n[(it - 3) % 3][0][0],
-                            *npp = &sm.n[(it - 2) % 3][0][0];
-                const int c = (sy + 1) * GX + (sx + 1);  // centre in the geometry region
-                float kap = 0.f;
-#pragma unroll
-                for (int cz = -1; cz <= 1; ++cz)
-#pragma unroll
-                    for (int cy = -1; cy <= 1; ++cy)
-#pragma unroll
-                        for (int cx = -1; cx <= 1; ++cx) {
-                            const bool lead = cx > 0 || (cx == 0 && (cy > 0 || (cy == 0 && cz > 0)));
-                            if (!lead) continue;
-                            const float *na = cz > 0 ? npp : (cz < 0 ? nm : n0p);
-                            const float *nb = cz > 0 ? nm : (cz < 0 ? npp : n0p);
-                            const int ia = c + cy * GX + cx, ib = c - cy * GX - cx;
-                            const float w = 3.0f * w27(cx, cy, cz);
-                            if (cx) kap = fmaf(w * cx, na[ia] - nb[ib], kap);
-                            if (cy) kap = fmaf(w * cy, na[NGEO + ia] - nb[NGEO + ib], kap);
-                            if (cz) kap = fmaf(w * cz, na[2 * NGEO + ia] - nb[2 * NGEO + ib], kap);
-                        }
+                const float kap = 0.5f * (w1sum(cA, cB, cC) + (eC - eA));
                 const int zr = r;
                 const bool bnd = src_bnd_xy || (!g.per[2] && (zr <= 0 || zr >= g.nz - 1));
                 const float a = bnd ? 0.f : -sigma * kap;
@@ -330,9 +346,11 @@ __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, St
                 F0 = a * Gs[sidx];
                 F1 = a * Gs[NSRC + sidx];
                 F2 = a * Gs[2 * NSRC + sidx];
-                n0 = n0p[c];
-                n1 = n0p[NGEO + c];
-                n2 = n0p[2 * NGEO + c];
+                const float *nr = &sm.n[(it - 1) & 1][0][0];
+                const int c = (sy + 1) * GX + (sx + 1);
+                n0 = nr[c];
+                n1 = nr[NGEO + c];
+                n2 = nr[2 * NGEO + c];
                 phis = sm.phi[(it - 2) & 3][(sy + 2) * PX + (sx + 2)];
             }
 
@@ -543,6 +561,32 @@ __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, St
     }
 }
 
+
+template <int ST>
+__global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, StateView in, StateView out, int lz,
+                                                   int tiles_x, int tiles_y, unsigned long long step_next) {
+    __shared__ Smem sm;
+    step_fused<ST>(sm, g, ph, sc, in, out, lz, tiles_x, tiles_y, step_next, xcd_work_item(blockIdx.x, gridDim.x));
+}
+
+// Several lattices in one launch: the work items of domain k are
+// [work_begin, work_begin + tiles * chunks); domains are sorted by work_begin.
+template <int ST>
+__global__ __launch_bounds__(NT) void k_step_fused_multi(const FusedDomain *__restrict__ doms, int ndom) {
+    __shared__ Smem sm;
+    const int w = xcd_work_item(blockIdx.x, gridDim.x);
+    int lo = 0, hi = ndom - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (doms[mid].work_begin <= w)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const FusedDomain &d = doms[lo];
+    step_fused<ST>(sm, d.g, d.ph, d.sc, d.in, d.out, d.lz, d.tiles_x, d.tiles_y, d.step_next, w - d.work_begin);
+}
+
 }  // namespace fused
 
 // z planes per workgroup: the fixed choice of tslb_set_kernel, else the longest
@@ -557,6 +601,23 @@ int fused_chunk(const tslb_ctx *c) {
     return (int)std::max(4LL, std::min(64LL, lz));
 }
 
+FusedDomain fused_domain(const tslb_ctx *c, StateView in, StateView out, int64_t step_next, int work_begin) {
+    using namespace fused;
+    FusedDomain d;
+    d.g = c->geo;
+    d.ph = c->phys;
+    d.sc = c->scales;
+    d.in = in;
+    d.out = out;
+    d.step_next = (unsigned long long)step_next;
+    d.lz = fused_chunk(c);
+    d.tiles_x = (c->geo.nx + TX - 1) / TX;
+    d.tiles_y = (c->geo.ny + TY - 1) / TY;
+    d.work_begin = work_begin;
+    d.work_count = d.tiles_x * d.tiles_y * ((c->geo.nz + d.lz - 1) / d.lz);
+    return d;
+}
+
 // Launch the fused step over the whole lattice.
 hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int lz, int64_t step_next,
                              hipStream_t s) {
@@ -564,18 +625,36 @@ hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int
     const int tiles_x = (c->geo.nx + TX - 1) / TX, tiles_y = (c->geo.ny + TY - 1) / TY;
     const int chunks = (c->geo.nz + lz - 1) / lz;
     const unsigned blocks = (unsigned)tiles_x * tiles_y * chunks;
+    const unsigned long long sn = (unsigned long long)step_next;
     switch (c->storage) {
     case ST_FP32:
         hipLaunchKernelGGL(k_step_fused<ST_FP32>, dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in, out,
-                           lz, tiles_x, tiles_y, (unsigned long long)step_next, c->has_boundary ? 1 : 0);
+                           lz, tiles_x, tiles_y, sn);
         break;
     case ST_FP16:
         hipLaunchKernelGGL(k_step_fused<ST_FP16>, dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in, out,
-                           lz, tiles_x, tiles_y, (unsigned long long)step_next, c->has_boundary ? 1 : 0);
+                           lz, tiles_x, tiles_y, sn);
         break;
     default:
         hipLaunchKernelGGL(k_step_fused<ST_BF16>, dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in, out,
-                           lz, tiles_x, tiles_y, (unsigned long long)step_next, c->has_boundary ? 1 : 0);
+                           lz, tiles_x, tiles_y, sn);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_fused_multi(const FusedDomain *doms, int ndom, int total_work, int storage, hipStream_t s) {
+    using namespace fused;
+    if (ndom <= 0 || total_work <= 0) return hipSuccess;
+    switch (storage) {
+    case ST_FP32:
+        hipLaunchKernelGGL(k_step_fused_multi<ST_FP32>, dim3(total_work), dim3(NT), 0, s, doms, ndom);
+        break;
+    case ST_FP16:
+        hipLaunchKernelGGL(k_step_fused_multi<ST_FP16>, dim3(total_work), dim3(NT), 0, s, doms, ndom);
+        break;
+    default:
+        hipLaunchKernelGGL(k_step_fused_multi<ST_BF16>, dim3(total_work), dim3(NT), 0, s, doms, ndom);
         break;
     }
     return hipGetLastError();

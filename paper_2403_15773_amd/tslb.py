@@ -28,6 +28,8 @@ EXPORTS = [
     "tslb_moments", "tslb_phase", "tslb_state_bytes", "tslb_get_state_raw", "tslb_set_state_raw",
     "tslb_diagnostics", "tslb_step_index", "tslb_set_timing", "tslb_last_step_kernel_ms", "tslb_set_kernel",
     "tslb_copy_bandwidth", "tslb_destroy", "tslb_last_error",
+    "tslb_group_create", "tslb_group_admit", "tslb_group_poll", "tslb_group_status", "tslb_group_destroy",
+    "tslb_group_last_error",
 ]
 KERNEL_FUSED, KERNEL_GATHER = 0, 1
 
@@ -95,6 +97,13 @@ def load_library(path: str = LIB_PATH):
                                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
             "tslb_destroy": (None, [vp]),
             "tslb_last_error": (ctypes.c_char_p, [vp]),
+            "tslb_group_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, vp, ctypes.POINTER(vp)]),
+            "tslb_group_admit": (ctypes.c_int, [vp, vp, ctypes.c_int64]),
+            "tslb_group_poll": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+            "tslb_group_status": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int32),
+                                                 ctypes.POINTER(ctypes.c_int64)]),
+            "tslb_group_destroy": (None, [vp]),
+            "tslb_group_last_error": (ctypes.c_char_p, [vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -243,3 +252,59 @@ class Simulation:
     def set_kernel(self, kernel="fused", chunk_z=0):
         k = {"fused": KERNEL_FUSED, "gather": KERNEL_GATHER}[kernel] if isinstance(kernel, str) else int(kernel)
         self._check(self.lib.tslb_set_kernel(self.h, k, int(chunk_z)))
+
+
+class Group:
+    """A serving group (``tslb_group``): admitted Simulations advance together,
+    one multi-domain step launch per :meth:`poll`."""
+
+    def __init__(self, hbm_budget_bytes: int, max_domains: int = 256, stream=None):
+        self.lib = load_library()
+        h = ctypes.c_void_p()
+        rc = self.lib.tslb_group_create(int(hbm_budget_bytes), int(max_domains), stream, ctypes.byref(h))
+        if rc != OK:
+            raise TslbError(rc, self.lib.tslb_group_last_error(None).decode())
+        self.h = h
+        self.max_domains = int(max_domains)
+        self._members = {}  # ctx handle value -> Simulation
+
+    def _check(self, rc):
+        if rc != OK:
+            raise TslbError(rc, self.lib.tslb_group_last_error(self.h).decode())
+
+    def admit(self, sim: Simulation, nsteps: int) -> bool:
+        """True if admitted; False if the HBM budget or the slots are full (defer)."""
+        rc = self.lib.tslb_group_admit(self.h, sim.h, int(nsteps))
+        if rc == E_NOMEM:
+            return False
+        self._check(rc)
+        self._members[sim.h.value] = sim
+        return True
+
+    def poll(self):
+        """Retire finished members (returned as Simulations) and launch the next step."""
+        cap = max(1, len(self._members))
+        arr = (ctypes.c_void_p * cap)()
+        n = ctypes.c_int32()
+        self._check(self.lib.tslb_group_poll(self.h, arr, cap, ctypes.byref(n)))
+        return [self._members.pop(arr[i]) for i in range(n.value)]
+
+    def status(self):
+        b, m, l = ctypes.c_size_t(), ctypes.c_int32(), ctypes.c_int64()
+        self._check(self.lib.tslb_group_status(self.h, ctypes.byref(b), ctypes.byref(m), ctypes.byref(l)))
+        return {"bytes_in_use": b.value, "members": m.value, "launches": l.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tslb_group_destroy(self.h)
+            self.h = None
+            self._members = {}
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,140 @@
+"""GPU checks of the serving group (continuous batching through the C-ABI).
+
+The step of one lattice reads and writes only that lattice, so a request run
+inside a mixed group must give bitwise the state it gets when run alone with
+tslb_step; admission by HBM budget must defer and later accept; a member is
+locked while the group owns it."""
+import numpy as np
+import pytest
+
+from paper_2403_15773_amd import serve
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print("[gpu-test] " + msg, flush=True)
+
+
+def _mix_requests():
+    """8 requests covering both set-ups and every box side, short runs."""
+    spec = [(32, "droplet", 800.0, 50.0, 37), (48, "jet", 2000.0, 300.0, 52), (64, "droplet", 1500.0, 20.0, 45),
+            (96, "jet", 600.0, 1000.0, 30), (128, "droplet", 3000.0, 100.0, 24), (32, "jet", 500.0, 10.0, 61),
+            (48, "droplet", 4000.0, 2000.0, 40), (128, "jet", 1000.0, 150.0, 28)]
+    return [serve.Request(i, 0.0, L, s, re, we, n, 1000 + i) for i, (L, s, re, we, n) in enumerate(spec)]
+
+
+def _alone(req):
+    from paper_2403_15773_amd.tslb import Simulation
+    p, f = serve.request_setup(req)
+    with Simulation(**p) as s:
+        s.set_state(**f)
+        s.step(req.steps)
+        return s.get_state_raw(), s.step_index
+
+
+def test_group_results_equal_alone_runs_bitwise():
+    from paper_2403_15773_amd.tslb import Group, Simulation
+    reqs = _mix_requests()
+    _say("group mix of %d requests (sides %s)" % (len(reqs), sorted({r.L for r in reqs})))
+    alone = {r.id: _alone(r) for r in reqs}
+    got = {}
+    with Group(hbm_budget_bytes=8 << 30, max_domains=8) as g:
+        sims = {}
+        waves = [reqs[:3], reqs[3:6], reqs[6:]]
+        polls = 0
+        while waves or g.status()["members"]:
+            if waves and polls % 9 == 0:  # requests join while others run
+                for r in waves.pop(0):
+                    p, f = serve.request_setup(r)
+                    s = Simulation(**p)
+                    s.set_state(**f)
+                    assert g.admit(s, r.steps)
+                    sims[s.h.value] = (r, s)
+            for s in g.poll():
+                r, _ = sims[s.h.value]
+                got[r.id] = (s.get_state_raw(), s.step_index)
+                s.close()
+            polls += 1
+            assert polls < 10000
+    assert sorted(got) == sorted(alone)
+    for r in reqs:
+        assert got[r.id][1] == alone[r.id][1] == r.steps
+        assert np.array_equal(got[r.id][0], alone[r.id][0]), "request %d (%s L=%d) differs" % (r.id, r.setup, r.L)
+
+
+def test_group_budget_defers_then_admits():
+    from paper_2403_15773_amd.tslb import Group, Simulation
+    _say("group HBM budget deferral")
+    a = serve.Request(0, 0.0, 32, "droplet", 1000.0, 100.0, 10, 1)
+    b = serve.Request(1, 0.0, 32, "jet", 1000.0, 100.0, 5, 2)
+    pa, fa = serve.request_setup(a)
+    pb, fb = serve.request_setup(b)
+    sa, sb = Simulation(**pa), Simulation(**pb)
+    sa.set_state(**fa)
+    sb.set_state(**fb)
+    from paper_2403_15773_amd.tslb import required_bytes
+    need = required_bytes(sa.params)  # both state buffers
+    assert need == required_bytes(sb.params) == 2 * sa.state_bytes
+    with Group(hbm_budget_bytes=need + need // 2, max_domains=4) as g:
+        assert g.admit(sa, a.steps)
+        assert not g.admit(sb, b.steps)  # over budget: defer
+        assert g.status()["bytes_in_use"] == need
+        done = []
+        while not done:
+            done = g.poll()
+        assert done[0] is sa and sa.step_index == 10
+        assert g.admit(sb, b.steps)
+        done = []
+        while not done:
+            done = g.poll()
+        assert done[0] is sb and sb.step_index == 5
+        assert g.status()["members"] == 0 and g.status()["bytes_in_use"] == 0
+    sa.close()
+    sb.close()
+
+
+def test_group_member_is_locked_and_zero_steps_retire():
+    from paper_2403_15773_amd.tslb import E_STATE, Group, Simulation, TslbError
+    _say("group member lock, zero-step admission")
+    r = serve.Request(0, 0.0, 32, "droplet", 1000.0, 100.0, 3, 5)
+    p, f = serve.request_setup(r)
+    s = Simulation(**p)
+    s.set_state(**f)
+    raw0 = s.get_state_raw()
+    with Group(hbm_budget_bytes=1 << 30, max_domains=2) as g:
+        assert g.admit(s, 0)
+        with pytest.raises(TslbError) as e:
+            s.step(1)
+        assert e.value.code == E_STATE
+        done = []
+        for _ in range(100):
+            done = g.poll()
+            if done:
+                break
+        assert done == [s] and s.step_index == 0
+        assert np.array_equal(s.get_state_raw(), raw0)
+        assert g.admit(s, 3)
+        with pytest.raises(TslbError):
+            g.admit(s, 1)  # already a member
+        assert g.poll() == []  # launches step 1 of 3
+    # destroying the group frees its members at the step they reached
+    assert s.step_index == 1
+    s.step(1)
+    assert s.step_index == 2
+    s.close()
+
+
+def test_small_serving_stream_completes():
+    from paper_2403_15773_amd.tslb import Group
+    reqs = serve.make_requests(12, rate=200.0, master_seed=9, sizes=(32, 48), re=(200.0, 600.0), steps=(50, 150))
+    _say("serving stream of %d requests" % len(reqs))
+    with Group(hbm_budget_bytes=256 << 20, max_domains=6) as g:
+        recs = serve.serve(reqs, serve.GpuBackend(g), 256 << 20, max_domains=6)
+    s = serve.summarise(recs)
+    _say("p50 %.3f s p99 %.3f s aggregate %.2f GLUPS unstable %d" % (
+        s["p50_latency_s"], s["p99_latency_s"], s["aggregate_glups"], s["unstable"]))
+    assert s["unstable"] == 0 and s["requests"] == 12
+    for rec in recs:
+        assert rec.extra["step"] == rec.req.steps
+        assert rec.req.arrival <= rec.admitted <= rec.done
