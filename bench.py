@@ -228,6 +228,8 @@ def main():
         "config": describe(a.workload, p) | {"storage": a.storage, "finite": m["finite"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, copy-kernel scaled)",
+                     "traffic_vs_algorithmic": traffic / (m["bpn"] * nodes) if traffic else None,
                      "kernel": "%s step" % a.kernel, "bytes_per_node": m["bpn"], "kernel_ms": m["kernel_ms"],
                      "copy_ceiling": copy["gbps"] if copy else None,
                      "frac_of_copy_ceiling": achieved / copy["gbps"] if (copy and achieved) else None},

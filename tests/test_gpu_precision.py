@@ -1,0 +1,81 @@
+"""Reduced-precision storage (moments stored as FP16 or BF16 scaled deviations
+rho'/U^2, u/U, Q/U^2 with U = 0.05; arithmetic and the phase field unchanged).
+
+Bars:
+* Laplace's law (static droplet, R = 6, 8, 10, 3000 steps): the pressure jump
+  with 16-bit storage within 2 % of the binary32 one, and binary32 within 5 %
+  of 2 sigma / R (the physics pin of the whole GPU path);
+* the 1e-3 per-field target against the FP64 oracle on the 32^3 droplet is NOT
+  met by 16-bit storage (measured worst field: FP16 1.3e-2, BF16 1.1e-1, both
+  in the stress P); the test bounds the measured error so that a regression
+  shows, and the target is kept as an expected failure;
+* conservation: the phase sum stays exact (fixed point), the mass drifts by the
+  storage rounding only.
+"""
+import numpy as np
+import pytest
+
+from paper_2403_15773_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+EPS = 1e-4
+CS2 = 1.0 / 3.0
+# measured worst per-field relative L-inf error after 200 steps of the 32^3
+# droplet (FP16 1.27e-2, BF16 1.11e-1), with head room for regressions only
+BOUND = {"fp16": 2.5e-2, "bf16": 2.0e-1}
+
+
+def _say(msg):
+    print("[gpu-test] " + msg, flush=True)
+
+
+def _droplet_errors(storage):
+    from test_gpu_parity import _f32, field_errors, run_both
+    p = inputs.droplet_params(32)
+    g, r = run_both(p, inputs.droplet(32, 8.0, 3.0, noise_amp=1e-3, seed=1), 200, storage=storage)
+    e = {k: v[0] for k, v in field_errors(g, r).items()}
+    _say("droplet32 %s vs oracle: " % storage + " ".join("%s=%.1e" % kv for kv in e.items()))
+    return e
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_reduced_storage_error_is_bounded(storage):
+    e = _droplet_errors(storage)
+    assert max(e.values()) <= BOUND[storage]
+    assert e["rho-1"] <= BOUND[storage] / 10 and e["phi"] <= BOUND[storage] / 10
+
+
+@pytest.mark.xfail(strict=True, reason="16-bit moment storage misses the 1e-3 per-field target (FP16 1.3e-2 in P)")
+def test_fp16_meets_1e3_target():
+    assert max(_droplet_errors("fp16").values()) <= 1e-3
+
+
+def _laplace_dp(radius, storage, steps=3000):
+    from paper_2403_15773_amd.tslb import Simulation
+    from test_gpu_parity import _f32
+    n, W, sigma = 32, 3.0, 0.01
+    st = _f32(inputs.droplet(n, radius, W, noise_amp=0.0, rho_inside=2 * sigma / (radius * CS2)))
+    with Simulation(nx=n, ny=n, nz=n, nu=0.1, sigma=sigma, width=W, eps=EPS, storage=storage) as s:
+        s.set_state(**st)
+        s.step(steps)
+        rho = 1.0 + s.moments()[0].astype(np.float64)
+        d = s.diagnostics()
+    x, y, z = inputs.grid_coords(n, n, n)
+    r = np.sqrt((x - n / 2) ** 2 + (y - n / 2) ** 2 + (z - n / 2) ** 2)
+    dp = CS2 * (rho[r <= radius - W].mean() - rho[r >= radius + W + 2].mean())
+    return dp * radius / (2 * sigma), d
+
+
+@pytest.mark.parametrize("radius", [6.0, 8.0, 10.0])
+def test_laplace_law_binary32_and_16_bit(radius):
+    ref, d32 = _laplace_dp(radius, "fp32")
+    _say("Laplace R=%g fp32: dp R/(2 sigma) = %.4f" % (radius, ref))
+    assert ref == pytest.approx(1.0, abs=0.05)
+    for storage in ("fp16", "bf16"):
+        v, d = _laplace_dp(radius, storage)
+        _say("Laplace R=%g %s: %.4f (%.2e vs fp32)" % (radius, storage, v, v / ref - 1))
+        assert v == pytest.approx(ref, rel=0.02)
+        assert d["finite"]
+        # the phase field is stored in fixed point whatever the moment storage
+        assert d["phase"] == d32["phase"]
