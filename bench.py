@@ -29,7 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
-BYTES_PER_NODE = {"fp32": 88, "fp16": 48, "bf16": 48}
+BYTES_PER_NODE = {"fp32": 88, "fp16": 48, "bf16": 48, "fp16q": 64}
 # HBM traffic of the fused step from rocprofv3 counters, valid while the kernel
 # sources hash to the value recorded next to the figures
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_step_jet128_traffic.txt")
@@ -42,8 +42,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="jet128", choices=["jet128", "jet512", "droplet32"])
-    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"])
-    ap.add_argument("--variants", default="fp16,bf16", help="other storage types timed on the same workload")
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16", "fp16q"])
+    ap.add_argument("--variants", default="fp16,bf16,fp16q", help="other storage types timed on the same workload")
     ap.add_argument("--serve", type=int, default=256, help="requests in the serving stream (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-oracle sample budget (0 = skip)")
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the copy-kernel ceiling probe (0 = skip)")

@@ -61,11 +61,16 @@ enum {
     TSLB_BC_NOSLIP = 4    /* velocity zero; rest copied */
 };
 
-/* Storage type of the ten moment planes (phi is always binary32). */
+/* Storage type of the ten moment planes (the phase field is always one 32-bit
+ * plane, fixed point with 30 fractional bits).  Bytes per node and buffer:
+ * FP32 44, FP16 and BF16 24, FP16Q 32.  Arithmetic is binary32 in every case. */
 enum {
     TSLB_STORE_FP32 = 0,
-    TSLB_STORE_FP16 = 1, /* scaled deviations rho'/U^2, ubar/U, Q/U^2, round to nearest even */
-    TSLB_STORE_BF16 = 2
+    TSLB_STORE_FP16 = 1,  /* scaled deviations rho'/U^2, ubar/U, Q/U^2, round to nearest even */
+    TSLB_STORE_BF16 = 2,  /* the same in bfloat16 */
+    TSLB_STORE_FP16Q = 3  /* rho' and ubar in binary32, only the stress Q/U^2 in binary16: rounding
+                             of rho' leaks into the small stress through neighbour differences,
+                             so keeping it (and ubar) exact meets a 1e-3 moment error where FP16 does not */
 };
 
 /* Step kernels (tslb_set_kernel). */

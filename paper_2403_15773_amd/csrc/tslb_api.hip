@@ -68,7 +68,7 @@ bool validate(const tslb_params *p, std::string &why) {
     if (!(1.0 / (3.0 * p->nu + 0.5) < 2.0)) { why = "omega must stay below 2"; return false; }
     if (!(p->sigma >= 0.0) || !std::isfinite(p->sigma)) { why = "sigma must be >= 0"; return false; }
     if (!(p->width > 0.0) || !std::isfinite(p->width)) { why = "width must be positive"; return false; }
-    if (p->storage < TSLB_STORE_FP32 || p->storage > TSLB_STORE_BF16) { why = "unknown storage"; return false; }
+    if (p->storage < TSLB_STORE_FP32 || p->storage > TSLB_STORE_FP16Q) { why = "unknown storage"; return false; }
     if (p->check_interval < 0) { why = "check_interval must be >= 0"; return false; }
     if (p->bc[4] == TSLB_BC_INLET && !(p->inlet_d > 0.0)) { why = "inlet_d must be positive"; return false; }
     return true;
@@ -196,8 +196,7 @@ int tslb_create(const tslb_params *p, tslb_ctx **out) {
         }
         c->owns_base = true;
     }
-    size_t esz = c->storage == TSLB_STORE_FP32 ? 4 : 2;
-    size_t mom_bytes = ((size_t)kPlanes * g.ld * esz + 255) / 256 * 256;
+    const size_t mom_bytes = moment_bytes(c->storage, g.ld);
     for (int b = 0; b < 2; ++b) {
         char *base = (char *)c->base + b * c->buffer_bytes;
         c->buf[b].mom = base;

@@ -48,7 +48,10 @@ struct Scales {
 
 // ---- storage traits -------------------------------------------------------
 
-enum { ST_FP32 = 0, ST_FP16 = 1, ST_BF16 = 2 };
+// FP32: ten binary32 planes.  FP16 / BF16: ten 16-bit planes holding the scaled
+// deviations rho'/U^2, ubar/U, Q/U^2.  FP16Q: rho' and ubar in binary32, only
+// the stress Q in binary16 (Q/U^2).
+enum { ST_FP32 = 0, ST_FP16 = 1, ST_BF16 = 2, ST_FP16Q = 3 };
 
 template <int ST> struct Store;
 
@@ -77,6 +80,44 @@ template <> struct Store<ST_BF16> {
         p[i] = (uint16_t)(r >> 16);
     }
 };
+
+// Bytes of the ten moment planes of one state buffer (planes of ld elements),
+// rounded up to 256 so that the phase plane that follows is aligned.
+__host__ __device__ inline size_t moment_bytes(int storage, long long ld) {
+    const size_t per_node = storage == ST_FP32 ? 40 : (storage == ST_FP16Q ? 28 : 20);
+    return ((size_t)ld * per_node + 255) / 256 * 256;
+}
+
+// Moment p of node id (0: rho', 1-3: ubar, 4-9: Q) from the planes at mom, as
+// the binary32 physical value.  p is a compile-time constant at every call, so
+// the plane's type and scale are resolved statically.
+template <int ST>
+__device__ __forceinline__ float load_moment(const void *mom, long long ld, int p, long long id, const Scales &sc) {
+    if constexpr (ST == ST_FP32) {
+        return ((const float *)mom)[p * ld + id];
+    } else if constexpr (ST == ST_FP16Q) {
+        if (p < 4) return ((const float *)mom)[p * ld + id];
+        return Store<ST_FP16>::load((const _Float16 *)((const float *)mom + 4 * ld) + (p - 4) * ld, id, sc.s2);
+    } else {
+        using S = Store<ST>;
+        return S::load((const typename S::T *)mom + p * ld, id, (p >= 1 && p < 4) ? sc.s1 : sc.s2);
+    }
+}
+
+template <int ST>
+__device__ __forceinline__ void store_moment(void *mom, long long ld, int p, long long id, float v, const Scales &sc) {
+    if constexpr (ST == ST_FP32) {
+        ((float *)mom)[p * ld + id] = v;
+    } else if constexpr (ST == ST_FP16Q) {
+        if (p < 4)
+            ((float *)mom)[p * ld + id] = v;
+        else
+            Store<ST_FP16>::store((_Float16 *)((float *)mom + 4 * ld) + (p - 4) * ld, id, v, sc.inv_s2);
+    } else {
+        using S = Store<ST>;
+        S::store((typename S::T *)mom + p * ld, id, v, (p >= 1 && p < 4) ? sc.inv_s1 : sc.inv_s2);
+    }
+}
 
 // ---- fixed-point phase field ----------------------------------------------
 

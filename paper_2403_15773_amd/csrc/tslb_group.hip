@@ -44,6 +44,8 @@ struct tslb_group {
 
 namespace {
 
+constexpr int kStorageTypes = 4;  // TSLB_STORE_FP32 .. TSLB_STORE_FP16Q
+
 int gfail(tslb_group *g, int code, const std::string &msg) {
     if (g)
         g->err = msg;
@@ -114,8 +116,8 @@ int tslb_group_create(size_t hbm_budget_bytes, int32_t max_domains, void *stream
     g->budget = hbm_budget_bytes;
     g->max_domains = max_domains;
     hipError_t e = hipGetDevice(&g->device);
-    // three storage types share one table of 3 * max_domains records per slot
-    const size_t tab = 3 * (size_t)max_domains * sizeof(FusedDomain);
+    // the storage types share one table of kStorageTypes * max_domains records per slot
+    const size_t tab = kStorageTypes * (size_t)max_domains * sizeof(FusedDomain);
     for (int s = 0; e == hipSuccess && s < tslb_group::kRing; ++s) {
         e = hipHostMalloc((void **)&g->h_tab[s], tab, hipHostMallocDefault);
         if (e == hipSuccess) e = hipMalloc((void **)&g->d_tab[s], tab);
@@ -201,8 +203,8 @@ int tslb_group_poll(tslb_group *g, tslb_ctx **done, int32_t cap, int32_t *ndone)
     }
     FusedDomain *h = g->h_tab[slot];
     int nrec = 0;
-    int first[3] = {0, 0, 0}, count[3] = {0, 0, 0}, work[3] = {0, 0, 0};
-    for (int st = 0; st < 3; ++st) {
+    int first[kStorageTypes] = {}, count[kStorageTypes] = {}, work[kStorageTypes] = {};
+    for (int st = 0; st < kStorageTypes; ++st) {
         first[st] = nrec;
         for (tslb_group::Member &m : g->members) {
             tslb_ctx *c = m.ctx;
@@ -215,7 +217,7 @@ int tslb_group_poll(tslb_group *g, tslb_ctx **done, int32_t cap, int32_t *ndone)
     }
     GHIP_TRY(g, hipMemcpyAsync(g->d_tab[slot], h, (size_t)nrec * sizeof(FusedDomain), hipMemcpyHostToDevice,
                                g->stream));
-    for (int st = 0; st < 3; ++st)
+    for (int st = 0; st < kStorageTypes; ++st)
         if (count[st]) GHIP_TRY(g, launch_step_fused_multi(g->d_tab[slot] + first[st], count[st], work[st], st, g->stream));
     GHIP_TRY(g, hipEventRecord(g->ev[slot], g->stream));
     g->slot_launch[slot] = id;

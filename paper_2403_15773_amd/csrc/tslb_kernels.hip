@@ -12,9 +12,7 @@ size_t plane_elems(long long N) { return (size_t)((N + 63) / 64 * 64); }
 
 size_t state_buffer_bytes(long long N, int storage) {
     size_t ld = plane_elems(N);
-    size_t esz = storage == ST_FP32 ? 4 : 2;
-    size_t mom = ((size_t)kPlanes * ld * esz + 255) / 256 * 256;
-    return mom + ld * 4;
+    return moment_bytes(storage, (long long)ld) + ld * 4;
 }
 
 __device__ __forceinline__ void decompose(const Geo &g, long long id, int &x, int &y, int &z) {
@@ -24,36 +22,19 @@ __device__ __forceinline__ void decompose(const Geo &g, long long id, int &x, in
     z = (int)(r / g.ny);
 }
 
-template <int ST>
-__device__ __forceinline__ const typename Store<ST>::T *plane(const StateView &v, const Geo &g, int p) {
-    return (const typename Store<ST>::T *)v.mom + (long long)p * g.ld;
-}
-template <int ST>
-__device__ __forceinline__ typename Store<ST>::T *plane_w(const StateView &v, const Geo &g, int p) {
-    return (typename Store<ST>::T *)v.mom + (long long)p * g.ld;
-}
-
 // Load the ten raw moments of node id: m[0] = rho', m[1..3] = ubar, m[4..9] = Q.
 template <int ST>
 __device__ __forceinline__ void load_raw(const StateView &v, const Geo &g, const Scales &sc, long long id,
                                          float m[10]) {
-    using S = Store<ST>;
-    m[0] = S::load(plane<ST>(v, g, 0), id, sc.s2);
 #pragma unroll
-    for (int p = 1; p < 4; ++p) m[p] = S::load(plane<ST>(v, g, p), id, sc.s1);
-#pragma unroll
-    for (int p = 4; p < 10; ++p) m[p] = S::load(plane<ST>(v, g, p), id, sc.s2);
+    for (int p = 0; p < 10; ++p) m[p] = load_moment<ST>(v.mom, g.ld, p, id, sc);
 }
 
 template <int ST>
 __device__ __forceinline__ void store_raw(const StateView &v, const Geo &g, const Scales &sc, long long id,
                                           const float m[10]) {
-    using S = Store<ST>;
-    S::store(plane_w<ST>(v, g, 0), id, m[0], sc.inv_s2);
 #pragma unroll
-    for (int p = 1; p < 4; ++p) S::store(plane_w<ST>(v, g, p), id, m[p], sc.inv_s1);
-#pragma unroll
-    for (int p = 4; p < 10; ++p) S::store(plane_w<ST>(v, g, p), id, m[p], sc.inv_s2);
+    for (int p = 0; p < 10; ++p) store_moment<ST>(v.mom, g.ld, p, id, m[p], sc);
 }
 
 // ---- interface geometry, materialised (set-state, readout, gather step) ----
@@ -312,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_step_gather(Geo g, Phys ph, Scales s
     if (is_boundary_node(g, x, y, z)) return;
     const long long ld = g.ld;
     const float omega1 = 1.0f - ph.omega;
-    const float rp_x = Store<ST>::load(plane<ST>(in, g, 0), id, sc.s2);
+    const float rp_x = load_moment<ST>(in.mom, g.ld, 0, id, sc);
     float acc[10];
 #pragma unroll
     for (int p = 0; p < 10; ++p) acc[p] = 0.f;
@@ -408,7 +389,8 @@ hipError_t launch_geometry(const tslb_ctx *c, const int32_t *phi, float *geo, hi
         switch (ST_VAR) {                                                           \
         case ST_FP32: hipLaunchKernelGGL(KERNEL<ST_FP32>, __VA_ARGS__); break;      \
         case ST_FP16: hipLaunchKernelGGL(KERNEL<ST_FP16>, __VA_ARGS__); break;      \
-        default: hipLaunchKernelGGL(KERNEL<ST_BF16>, __VA_ARGS__); break;           \
+        case ST_BF16: hipLaunchKernelGGL(KERNEL<ST_BF16>, __VA_ARGS__); break;      \
+        default: hipLaunchKernelGGL(KERNEL<ST_FP16Q>, __VA_ARGS__); break;          \
         }                                                                           \
     } while (0)
 

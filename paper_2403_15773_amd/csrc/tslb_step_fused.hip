@@ -133,9 +133,6 @@ template <int ST>
 __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &ph, const Scales &sc,
                                            const StateView &in, const StateView &out, int lz, int tiles_x,
                                            int tiles_y, unsigned long long step_next, int w) {
-    using S = Store<ST>;
-    using T = typename S::T;
-
     const int tile = w % (tiles_x * tiles_y);
     const int chunk = w / (tiles_x * tiles_y);
     // The tile owns columns [xo, xo + TX) x [yo, yo + TY); its origin (x0, y0) is
@@ -219,12 +216,8 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
     auto plane_of = [&](int z) { return wrap_or_clamp(z, g.nz, g.per[2]); };
     auto load_moments = [&](int z, float m[10]) {
         const long long id = col_src + plane * plane_of(z);
-        const T *base = (const T *)in.mom;
-        m[0] = S::load(base, id, sc.s2);
 #pragma unroll
-        for (int p = 1; p < 4; ++p) m[p] = S::load(base + p * g.ld, id, sc.s1);
-#pragma unroll
-        for (int p = 4; p < 10; ++p) m[p] = S::load(base + p * g.ld, id, sc.s2);
+        for (int p = 0; p < 10; ++p) m[p] = load_moment<ST>(in.mom, g.ld, p, id, sc);
     };
     auto load_phi = [&](int z, int32_t v[2]) {
         const long long zoff = plane * plane_of(z);
@@ -511,26 +504,9 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
                     m[8] = fmaf(-jx * inv, jz, m10.m1);
                     m[9] = fmaf(-jy * inv, jz, m01.m1);
                     const int32_t phin = PA + pdown;
-                    T *o = (T *)out.mom;
-                    // the node itself: interior, or on an x/y wall (face rule of step t+1)
-                    {
-                        float mo[10];
-#pragma unroll
-                        for (int k = 0; k < 10; ++k) mo[k] = m[k];
-                        int32_t po = phin;
-                        if (dxf | dyf) {
-                            const int face = boundary_face(g, gxs, gys, zd);
-                            apply_boundary_rule(ph, g, face, gxs, gys, step_next, mo, po);
-                        }
-                        const long long id = (long long)gxs + (long long)g.nx * gys + plane * zd;
-                        S::store(o, id, mo[0], sc.inv_s2);
-#pragma unroll
-                        for (int k = 1; k < 4; ++k) S::store(o + k * g.ld, id, mo[k], sc.inv_s1);
-#pragma unroll
-                        for (int k = 4; k < 10; ++k) S::store(o + k * g.ld, id, mo[k], sc.inv_s2);
-                        out.phi[id] = po;
-                    }
                     // the z walls of this column take the values of planes 1 and nz-2
+                    // (x_F of an edge node is interior in every coordinate, so the
+                    // image is made from the moments before any x/y rule)
                     if (!g.per[2] && (zd == 1 || zd == g.nz - 2)) {
                         const int zb = zd == 1 ? 0 : g.nz - 1;
                         float mb[10];
@@ -539,13 +515,20 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
                         int32_t pb = phin;
                         apply_boundary_rule(ph, g, zd == 1 ? 4 : 5, gxs, gys, step_next, mb, pb);
                         const long long ib = (long long)gxs + (long long)g.nx * gys + plane * zb;
-                        S::store(o, ib, mb[0], sc.inv_s2);
 #pragma unroll
-                        for (int k = 1; k < 4; ++k) S::store(o + k * g.ld, ib, mb[k], sc.inv_s1);
-#pragma unroll
-                        for (int k = 4; k < 10; ++k) S::store(o + k * g.ld, ib, mb[k], sc.inv_s2);
+                        for (int k = 0; k < 10; ++k) store_moment<ST>(out.mom, g.ld, k, ib, mb[k], sc);
                         out.phi[ib] = pb;
                     }
+                    // the node itself: interior, or on an x/y wall (face rule of step t+1)
+                    int32_t po = phin;
+                    if (dxf | dyf) {
+                        const int face = boundary_face(g, gxs, gys, zd);
+                        apply_boundary_rule(ph, g, face, gxs, gys, step_next, m, po);
+                    }
+                    const long long id = (long long)gxs + (long long)g.nx * gys + plane * zd;
+#pragma unroll
+                    for (int k = 0; k < 10; ++k) store_moment<ST>(out.mom, g.ld, k, id, m[k], sc);
+                    out.phi[id] = po;
                 }
                 // carry: plane r gets X(+1) = XC, X(0) = X0; plane r+1 gets X(+1) = Xp
 #pragma unroll
@@ -635,9 +618,13 @@ hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int
         hipLaunchKernelGGL(k_step_fused<ST_FP16>, dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in, out,
                            lz, tiles_x, tiles_y, sn);
         break;
-    default:
+    case ST_BF16:
         hipLaunchKernelGGL(k_step_fused<ST_BF16>, dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in, out,
                            lz, tiles_x, tiles_y, sn);
+        break;
+    default:
+        hipLaunchKernelGGL(k_step_fused<ST_FP16Q>, dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in,
+                           out, lz, tiles_x, tiles_y, sn);
         break;
     }
     return hipGetLastError();
@@ -653,8 +640,11 @@ hipError_t launch_step_fused_multi(const FusedDomain *doms, int ndom, int total_
     case ST_FP16:
         hipLaunchKernelGGL(k_step_fused_multi<ST_FP16>, dim3(total_work), dim3(NT), 0, s, doms, ndom);
         break;
-    default:
+    case ST_BF16:
         hipLaunchKernelGGL(k_step_fused_multi<ST_BF16>, dim3(total_work), dim3(NT), 0, s, doms, ndom);
+        break;
+    default:
+        hipLaunchKernelGGL(k_step_fused_multi<ST_FP16Q>, dim3(total_work), dim3(NT), 0, s, doms, ndom);
         break;
     }
     return hipGetLastError();

@@ -20,8 +20,8 @@ ABI_VERSION = 1
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSTABLE, E_STATE = 0, -1, -2, -3, -4, -5
 BC_PERIODIC, BC_FREESLIP, BC_INLET, BC_OUTFLOW, BC_NOSLIP = 0, 1, 2, 3, 4
-STORE_FP32, STORE_FP16, STORE_BF16 = 0, 1, 2
-STORAGE = {"fp32": STORE_FP32, "fp16": STORE_FP16, "bf16": STORE_BF16}
+STORE_FP32, STORE_FP16, STORE_BF16, STORE_FP16Q = 0, 1, 2, 3
+STORAGE = {"fp32": STORE_FP32, "fp16": STORE_FP16, "bf16": STORE_BF16, "fp16q": STORE_FP16Q}
 
 EXPORTS = [
     "tslb_params_init", "tslb_params_size", "tslb_required_bytes", "tslb_create", "tslb_set_state", "tslb_step", "tslb_sync",

@@ -50,6 +50,8 @@ def test_defaults_and_required_bytes(lib):
     assert lib.tslb_required_bytes(ctypes.byref(p)) == 2 * 11 * 4 * 32 ** 3
     p.storage = tslb.STORE_FP16
     assert lib.tslb_required_bytes(ctypes.byref(p)) == 2 * (10 * 2 + 4) * 32 ** 3
+    p.storage = tslb.STORE_FP16Q  # rho', ubar binary32 + six binary16 stress planes + phi
+    assert lib.tslb_required_bytes(ctypes.byref(p)) == 2 * (4 * 4 + 6 * 2 + 4) * 32 ** 3
     p.storage = tslb.STORE_FP32
     p.nx = 33  # 33*32*32 = 33792 = 528 * 64: still aligned
     assert lib.tslb_required_bytes(ctypes.byref(p)) == 2 * 11 * 4 * 33792

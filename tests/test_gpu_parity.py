@@ -254,3 +254,27 @@ def test_fused_matches_gather_on_full_jet():
     assert res["gather"]["u"][2].max() > 0.04  # the jet is there
     bad = {kk: v for kk, v in errs.items() if not v[0] <= 2 * TOL_FP32}
     assert not bad, bad
+
+
+def test_full_jet_step_matches_oracle_at_every_node():
+    """The 128 x 128 x 512 jet in the launch configuration the benchmark times
+    (automatic z chunk), developed for 300 steps on the GPU; one further GPU
+    step against one FP64 oracle step from the GPU's own state, every node."""
+    from oracle import Oracle
+    from paper_2403_15773_amd.tslb import Simulation
+    _say("full jet 128x128x512: GPU step 301 vs one oracle step from the GPU state at 300")
+    p = inputs.WORKLOADS["jet128"]["params"]
+    with Simulation(**p, eps=EPS) as s:
+        s.set_state_raw(np.zeros(s.state_bytes, np.uint8), step=0)  # quiescent
+        s.step(300)
+        g0 = s.physical()
+        s.step(1)
+        g1 = s.physical()
+    assert g0["u"][2].max() > 0.04  # the jet is there
+    o = Oracle(p["nx"], p["ny"], p["nz"], nu=p["nu"], sigma=p["sigma"], width=p["width"], eps=EPS, bc=p["bc"],
+               inlet_u=p["inlet_u"], inlet_d=p["inlet_d"], inlet_noise=p["inlet_noise"], seed=p["seed"])
+    o.set_physical(rho=1.0 + g0["rho_dev"].astype(np.float64), u=g0["u"], P=g0["P"], phi=g0["phi"], step=300)
+    o.step(1)
+    r1 = o.physical()
+    o.close()
+    assert_parity(g1, r1, TOL_FP32, "full-jet one step")
