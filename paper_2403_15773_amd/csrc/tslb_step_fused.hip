@@ -53,8 +53,8 @@ static_assert(NPHI <= 2 * NT && NGEO <= 2 * NT, "staging loops assume two items 
 
 struct Smem {
     int32_t phi[4][NPHI];      // fixed-point phase field, ring of 4 planes
-    float n[2][3][NGEO];       // unit normal, ring of 2 planes
-    float G[2][3][NSRC];       // gradient on the source region, ring of 2 planes
+    float n[3][3][NGEO];       // unit normal, ring of 3 planes
+    float G[3][3][NSRC];       // gradient on the source region, ring of 3 planes
     float xch[NXCH][NSRC];     // populations crossing columns
 };
 
@@ -190,14 +190,21 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
         col_phi[k] = (long long)gx + (long long)g.nx * gy;
     }
     // geometry items (<= 2 per thread): centre (gx, gy) in the 36 x 20 region.
-    // Waves are placed on the four SIMDs round-robin, and waves 8 and 9 (halo
-    // sources) put a third source wave on SIMDs 0 and 1; the NGEO - NT second
-    // items therefore go to waves 2 and 3 (SIMDs 2 and 3).
-    constexpr int kGeoExtraFirst = 128;
-    static_assert(NGEO - NT <= 128, "second geometry items must fit waves 2 and 3");
+    // Waves are placed on the four SIMDs round-robin (wave w on SIMD w % 4), and
+    // the geometry of the next plane is computed in the same phase as the
+    // collision, where SIMDs 0 and 1 already run three source waves (0, 4, 8 and
+    // 1, 5, 9) and SIMDs 2 and 3 two.  So waves 0-7 take one item each and the
+    // NGEO - 512 remaining items go to waves 2, 3, 6 and 7: every SIMD then
+    // issues about the same number of instructions in that phase.
+    static_assert(NDST == 512 && NGEO - NDST <= 256, "geometry item map assumes 8 destination waves");
     int geo_item[2];
-    geo_item[0] = t < NGEO ? t : -1;
-    geo_item[1] = (t >= kGeoExtraFirst && t < kGeoExtraFirst + (NGEO - NT)) ? NT + (t - kGeoExtraFirst) : -1;
+    geo_item[0] = t < NDST ? t : -1;
+    {
+        const int wv = t >> 6, lane = t & 63;
+        const int rank = wv == 2 ? 0 : wv == 3 ? 1 : wv == 6 ? 2 : wv == 7 ? 3 : -1;
+        const int i = NDST + rank * 64 + lane;
+        geo_item[1] = (rank >= 0 && i < NGEO) ? i : -1;
+    }
 
     const float omega1 = 1.0f - ph.omega;
     const float sigma = ph.sigma, gamma = ph.gamma, eps = ph.eps;
@@ -227,79 +234,37 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
     };
 
     const int nit = (z1 - z0) + 6;
-    // prologue: phase plane z0 - 3 staged before the loop
+    // prologue: phase planes z0 - 3 and z0 - 2 staged (slots 0, 1); z0 - 1 prefetched
     {
         int32_t v[2] = {0, 0};
         load_phi(z0 - 3, v);
 #pragma unroll
         for (int k = 0; k < 2; ++k)
             if (phi_item[k] >= 0) sm.phi[0][phi_item[k]] = v[k];
-        load_phi(z0 - 2, phi_next);
+        load_phi(z0 - 2, v);
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            if (phi_item[k] >= 0) sm.phi[1][phi_item[k]] = v[k];
+        load_phi(z0 - 1, phi_next);
     }
     __syncthreads();
 
+    // Iteration it works on three planes: p = z0 - 3 + it (geometry), q = p - 1
+    // (normal of the curvature sums) and r = p - 2 (sources), and finishes
+    // destination plane r - 1.  Rings: phi plane p at slot it mod 4, n and G of
+    // plane p at slot it mod 3.  Phase A (sources and geometry) and phase B
+    // (destinations and phase staging) are separated by barriers.
     for (int it = 0; it < nit; ++it) {
-        const int p = z0 - 3 + it;  // phase plane staged now (S1)
-        const int q = p - 1;        // plane of G and n (S2)
-        const int r = p - 2;        // source plane (S3, S4)
+        const int p = z0 - 3 + it;
+        const int r = p - 2;
 
-        // ---- S1: stage phi(p + 1) for the next iteration (slot it+1 mod 4) ----
-        if (it + 1 < nit) {
-#pragma unroll
-            for (int k = 0; k < 2; ++k)
-                if (phi_item[k] >= 0) sm.phi[(it + 1) & 3][phi_item[k]] = phi_next[k];
-        }
-        // ---- S2: G and n of plane q from phi planes q-1, q, q+1 ----
-        if (it >= 2) {
-            const int32_t *pm = sm.phi[(it - 2) & 3], *p0 = sm.phi[(it - 1) & 3], *pp = sm.phi[it & 3];
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const int i = geo_item[k];
-                if (i < 0) continue;
-                const int gxl = i % GX, gyl = i / GX;
-                const int c = (gyl + 1) * PX + (gxl + 1);  // centre in the phi region
-                float G0 = 0.f, G1 = 0.f, G2 = 0.f;
-#pragma unroll
-                for (int cz = -1; cz <= 1; ++cz)
-#pragma unroll
-                    for (int cy = -1; cy <= 1; ++cy)
-#pragma unroll
-                        for (int cx = -1; cx <= 1; ++cx) {
-                            const bool lead = cx > 0 || (cx == 0 && (cy > 0 || (cy == 0 && cz > 0)));
-                            if (!lead) continue;
-                            const int32_t *pa = cz > 0 ? pp : (cz < 0 ? pm : p0);
-                            const int32_t *pb = cz > 0 ? pm : (cz < 0 ? pp : p0);
-                            const int32_t a = pa[c + cy * PX + cx];
-                            const int32_t bb = pb[c - cy * PX - cx];
-                            const float d = (float)(a - bb);
-                            const float w = 3.0f * w27(cx, cy, cz) * kPhiUlp;
-                            if (cx) G0 = fmaf(w * cx, d, G0);
-                            if (cy) G1 = fmaf(w * cy, d, G1);
-                            if (cz) G2 = fmaf(w * cz, d, G2);
-                        }
-                const float inv = 1.0f / (sqrtf(G0 * G0 + G1 * G1 + G2 * G2) + eps);
-                float *n = &sm.n[it & 1][0][0];
-                n[i] = G0 * inv;
-                n[NGEO + i] = G1 * inv;
-                n[2 * NGEO + i] = G2 * inv;
-                const int ssx = gxl - 1, ssy = gyl - 1;
-                if (ssx >= 0 && ssx < SX && ssy >= 0 && ssy < SY) {
-                    float *Gs = &sm.G[it & 1][0][0];
-                    const int si = ssy * SX + ssx;
-                    Gs[si] = G0;
-                    Gs[NSRC + si] = G1;
-                    Gs[2 * NSRC + si] = G2;
-                }
-            }
-        }
-        // prefetch: phi plane p + 2 (staged next iteration), moments of plane r + 1
-        if (it + 2 < nit) load_phi(p + 2, phi_next);
+        // moments of source plane r + 1 for the next iteration
         float mom_cur[10];
 #pragma unroll
         for (int k = 0; k < 10; ++k) mom_cur[k] = mom[k];
         if (is_src && it >= 3) load_moments(r + 1, mom);
-        __syncthreads();
 
+        // ================= phase A =================
         // ---- S3a: per-column partial sums of the curvature stencil (plane q) ----
         // With w_i = w1(c_x) w1(c_y) w1(c_z), w1(0) = 2/3, w1(+-1) = 1/6, the stencil
         // kappa = 3 sum_i w_i c_i . n(x + c_i) factorises into sums over one plane:
@@ -309,7 +274,7 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
         //   E = sum_{cx,cy} w1(cx) w1(cy) n_z(x+cx, y+cy),
         // so each source keeps C and E of three planes in registers.
         if (it >= 2 && is_src) {
-            const float *nq = &sm.n[it & 1][0][0];
+            const float *nq = &sm.n[(it + 2) % 3][0][0];  // plane q, written one iteration ago
             const float *nyq = nq + NGEO, *nzq = nq + 2 * NGEO;
             const int c = (sy + 1) * GX + (sx + 1);  // centre in the geometry region
             const float Cx = w1sum(nq[c - GX + 1] - nq[c - GX - 1], nq[c + 1] - nq[c - 1], nq[c + GX + 1] - nq[c + GX - 1]);
@@ -335,11 +300,11 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
                 const int zr = r;
                 const bool bnd = src_bnd_xy || (!g.per[2] && (zr <= 0 || zr >= g.nz - 1));
                 const float a = bnd ? 0.f : -sigma * kap;
-                const float *Gs = &sm.G[(it - 1) & 1][0][0];
+                const float *Gs = &sm.G[(it + 1) % 3][0][0];  // plane r
                 F0 = a * Gs[sidx];
                 F1 = a * Gs[NSRC + sidx];
                 F2 = a * Gs[2 * NSRC + sidx];
-                const float *nr = &sm.n[(it - 1) & 1][0][0];
+                const float *nr = &sm.n[(it + 1) % 3][0][0];  // plane r
                 const int c = (sy + 1) * GX + (sx + 1);
                 n0 = nr[c];
                 n1 = nr[NGEO + c];
@@ -446,8 +411,54 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
                 sm.xch[33][sidx] = t0[4];
                 sm.xch[34][sidx] = tp[4];
             }
-            __syncthreads();
+        }
 
+        // ---- S2: G and n of plane p from phi planes p-1, p, p+1 (slots it-1, it, it+1) ----
+        if (it >= 1 && it + 2 <= nit) {
+            const int32_t *pm = sm.phi[(it + 3) & 3], *p0 = sm.phi[it & 3], *pp = sm.phi[(it + 1) & 3];
+            for (int k = 0; k < 2; ++k) {
+                const int i = geo_item[k];
+                if (i < 0) continue;
+                const int gxl = i % GX, gyl = i / GX;
+                const int c = (gyl + 1) * PX + (gxl + 1);  // centre in the phi region
+                float G0 = 0.f, G1 = 0.f, G2 = 0.f;
+#pragma unroll
+                for (int cz = -1; cz <= 1; ++cz)
+#pragma unroll
+                    for (int cy = -1; cy <= 1; ++cy)
+#pragma unroll
+                        for (int cx = -1; cx <= 1; ++cx) {
+                            const bool lead = cx > 0 || (cx == 0 && (cy > 0 || (cy == 0 && cz > 0)));
+                            if (!lead) continue;
+                            const int32_t *pa = cz > 0 ? pp : (cz < 0 ? pm : p0);
+                            const int32_t *pb = cz > 0 ? pm : (cz < 0 ? pp : p0);
+                            const int32_t a = pa[c + cy * PX + cx];
+                            const int32_t bb = pb[c - cy * PX - cx];
+                            const float d = (float)(a - bb);
+                            const float w = 3.0f * w27(cx, cy, cz) * kPhiUlp;
+                            if (cx) G0 = fmaf(w * cx, d, G0);
+                            if (cy) G1 = fmaf(w * cy, d, G1);
+                            if (cz) G2 = fmaf(w * cz, d, G2);
+                        }
+                const float inv = 1.0f / (sqrtf(G0 * G0 + G1 * G1 + G2 * G2) + eps);
+                float *n = &sm.n[it % 3][0][0];
+                n[i] = G0 * inv;
+                n[NGEO + i] = G1 * inv;
+                n[2 * NGEO + i] = G2 * inv;
+                const int ssx = gxl - 1, ssy = gyl - 1;
+                if (ssx >= 0 && ssx < SX && ssy >= 0 && ssy < SY) {
+                    float *Gs = &sm.G[it % 3][0][0];
+                    const int si = ssy * SX + ssx;
+                    Gs[si] = G0;
+                    Gs[NSRC + si] = G1;
+                    Gs[2 * NSRC + si] = G2;
+                }
+            }
+        }
+        __syncthreads();
+
+        // ================= phase B =================
+        if (it >= 4) {
             // ---- S5b/S6: gather at the destination and finish plane r - 1 ----
             if (is_dst) {
                 float gm[9], g0[9], gp[9];
@@ -541,6 +552,14 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
                 PC = pup;
             }
         }
+        // ---- S1: stage phi(p + 2) for the geometry of the next iteration ----
+        if (it + 3 <= nit) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                if (phi_item[k] >= 0) sm.phi[(it + 2) & 3][phi_item[k]] = phi_next[k];
+            if (it + 4 <= nit) load_phi(p + 3, phi_next);
+        }
+        __syncthreads();
     }
 }
 
