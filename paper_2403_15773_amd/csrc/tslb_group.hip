@@ -201,6 +201,18 @@ int tslb_group_poll(tslb_group *g, tslb_ctx **done, int32_t cap, int32_t *ndone)
         rc = refresh_completed(g);
         if (rc) return rc;
     }
+    // z chunks: a lattice alone takes short chunks to fill the device; in a
+    // batch the others fill it, so every member takes long chunks (less halo
+    // recomputed) once the batch has a workgroup per compute unit that way.
+    // The result does not depend on the chunk length.
+    long long long_work = 0;
+    int cus = 0;
+    for (const tslb_group::Member &m : g->members) {
+        if (m.remaining <= 0) continue;
+        long_work += fused_work_items(m.ctx, std::min(64, m.ctx->geo.nz));
+        cus = std::max(cus, m.ctx->cu_count);
+    }
+    const bool long_chunks = long_work >= cus;
     FusedDomain *h = g->h_tab[slot];
     int nrec = 0;
     int first[kStorageTypes] = {}, count[kStorageTypes] = {}, work[kStorageTypes] = {};
@@ -209,7 +221,8 @@ int tslb_group_poll(tslb_group *g, tslb_ctx **done, int32_t cap, int32_t *ndone)
         for (tslb_group::Member &m : g->members) {
             tslb_ctx *c = m.ctx;
             if (m.remaining <= 0 || c->storage != st) continue;
-            h[nrec] = fused_domain(c, c->buf[c->cur], c->buf[c->cur ^ 1], c->step + 1, work[st]);
+            h[nrec] = fused_domain(c, c->buf[c->cur], c->buf[c->cur ^ 1], c->step + 1, work[st],
+                                   long_chunks ? std::min(64, c->geo.nz) : 0);
             work[st] += h[nrec].work_count;
             ++nrec;
             ++count[st];

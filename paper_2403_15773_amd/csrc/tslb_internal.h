@@ -94,8 +94,12 @@ hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int
                              hipStream_t s);
 int fused_chunk(const tslb_ctx *c);
 // Describe one step of ctx c (in -> out) as a domain of a multi-domain launch
-// whose work items start at work_begin.
-FusedDomain fused_domain(const tslb_ctx *c, StateView in, StateView out, int64_t step_next, int work_begin);
+// whose work items start at work_begin; lz > 0 fixes the z chunk (else the
+// lattice's own choice).
+FusedDomain fused_domain(const tslb_ctx *c, StateView in, StateView out, int64_t step_next, int work_begin,
+                         int lz = 0);
+// Work items of one fused step of ctx c with z chunk lz.
+int fused_work_items(const tslb_ctx *c, int lz);
 // One fused step of every domain of a device table (all of one storage type).
 hipError_t launch_step_fused_multi(const FusedDomain *doms, int ndom, int total_work, int storage, hipStream_t s);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);

@@ -603,7 +603,13 @@ int fused_chunk(const tslb_ctx *c) {
     return (int)std::max(4LL, std::min(64LL, lz));
 }
 
-FusedDomain fused_domain(const tslb_ctx *c, StateView in, StateView out, int64_t step_next, int work_begin) {
+int fused_work_items(const tslb_ctx *c, int lz) {
+    using namespace fused;
+    return ((c->geo.nx + TX - 1) / TX) * ((c->geo.ny + TY - 1) / TY) * ((c->geo.nz + lz - 1) / lz);
+}
+
+FusedDomain fused_domain(const tslb_ctx *c, StateView in, StateView out, int64_t step_next, int work_begin,
+                         int lz) {
     using namespace fused;
     FusedDomain d;
     d.g = c->geo;
@@ -612,7 +618,7 @@ FusedDomain fused_domain(const tslb_ctx *c, StateView in, StateView out, int64_t
     d.in = in;
     d.out = out;
     d.step_next = (unsigned long long)step_next;
-    d.lz = fused_chunk(c);
+    d.lz = lz > 0 ? lz : fused_chunk(c);
     d.tiles_x = (c->geo.nx + TX - 1) / TX;
     d.tiles_y = (c->geo.ny + TY - 1) / TY;
     d.work_begin = work_begin;

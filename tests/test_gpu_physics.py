@@ -1,0 +1,39 @@
+"""Physics pins of the GPU path itself (besides parity with the oracle):
+a shear wave decays at nu = c_s^2 (1/omega - 1/2) (Methodology, Eqs. 3-4)."""
+import numpy as np
+import pytest
+
+from paper_2403_15773_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+CS2 = 1.0 / 3.0
+
+
+@pytest.mark.parametrize("nu", [0.01, 0.05])
+def test_taylor_green_shear_wave_viscosity(nu):
+    from paper_2403_15773_amd.tslb import Simulation
+    L, A = 64, 1e-4
+    k = 2 * np.pi / L
+    omega = 1.0 / (3 * nu + 0.5)
+    st = inputs.quiescent(4, L, 4)
+    y = np.arange(L)[None, :, None] * np.ones((4, L, 4))
+    st["u"][0] = A * np.sin(k * y)
+    # first-order Chapman-Enskog non-equilibrium stress: P_xy = -(rho c_s^2 / omega) du_x/dy
+    st["P"][3] = -(CS2 / omega) * A * k * np.cos(k * y)
+    f = {"rho_dev": np.zeros((4, L, 4), np.float32), "u": st["u"].astype(np.float32),
+         "P": st["P"].astype(np.float32), "phi": st["phi"].astype(np.float32)}
+    basis = np.sin(k * np.arange(L))
+    ts, amps = [], []
+    with Simulation(nx=4, ny=L, nz=4, nu=nu, sigma=0.0) as s:
+        s.set_state(**f)
+        s.step(50)
+        for _ in range(20):
+            ux = s.moments()[1][0].astype(np.float64).mean(axis=(0, 2))
+            ts.append(s.step_index)
+            amps.append(2.0 / L * (ux * basis).sum())
+            s.step(50)
+    rate = -np.polyfit(ts, np.log(amps), 1)[0]
+    print("[gpu-test] shear wave nu=%g: fitted %.6g, expected %.6g" % (nu, rate / k ** 2, CS2 * (1 / omega - 0.5)),
+          flush=True)
+    assert rate / k ** 2 == pytest.approx(CS2 * (1 / omega - 0.5), rel=0.01)
