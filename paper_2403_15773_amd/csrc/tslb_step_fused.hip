@@ -76,6 +76,13 @@ __device__ __forceinline__ float tr3_m0(float am, float a0, float ap) {
     return fmaf((am - a0) + (ap - a0), 1.0f / 6.0f, a0);
 }
 
+// 1/x for x near 1 (a density): the hardware reciprocal refined by one
+// Newton-Raphson step, e = 1 - x r, r' = r + r e, within an ulp of 1/x.
+__device__ __forceinline__ float recip(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 // Weighted three-point sum with the one-dimensional D3Q27 weights:
 // (1/6) m + (2/3) z + (1/6) p.
 __device__ __forceinline__ float w1sum(float m, float z, float p) { return fmaf(z, 2.0f / 3.0f, (m + p) * (1.0f / 6.0f)); }
@@ -197,6 +204,7 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
     // NGEO - 512 remaining items go to waves 2, 3, 6 and 7: every SIMD then
     // issues about the same number of instructions in that phase.
     static_assert(NDST == 512 && NGEO - NDST <= 256, "geometry item map assumes 8 destination waves");
+    static_assert(GX >= 32 && GX < 64, "geometry rows are split into 32 + (GX - 32) columns");
     int geo_item[2];
     geo_item[0] = t < NDST ? t : -1;
     {
@@ -318,7 +326,7 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
             if (is_src) {
                 const float rp = mom_cur[0];
                 const float rho = 1.0f + rp;
-                const float inv = 1.0f / rho;
+                const float inv = recip(rho);
                 const float hF = 0.5f * inv, qF = 0.25f * inv;
                 const float u0 = fmaf(hF, F0, mom_cur[1]), u1 = fmaf(hF, F1, mom_cur[2]), u2 = fmaf(hF, F2, mom_cur[3]);
                 const float Pxx = fmaf(qF * F0, F0, mom_cur[4]), Pyy = fmaf(qF * F1, F1, mom_cur[5]);
@@ -419,7 +427,12 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
             for (int k = 0; k < 2; ++k) {
                 const int i = geo_item[k];
                 if (i < 0) continue;
-                const int gxl = i % GX, gyl = i / GX;
+                // items 0 .. 32 GY - 1 cover columns 0-31 of each row, one row per
+                // half-wave (contiguous LDS addresses, no bank conflicts); the
+                // rest cover columns 32 .. GX - 1
+                const int gxl = i < 32 * GY ? (i & 31) : 32 + (i - 32 * GY) % (GX - 32);
+                const int gyl = i < 32 * GY ? (i >> 5) : (i - 32 * GY) / (GX - 32);
+                const int gi = gyl * GX + gxl;  // position in the geometry region
                 const int c = (gyl + 1) * PX + (gxl + 1);  // centre in the phi region
                 float G0 = 0.f, G1 = 0.f, G2 = 0.f;
 #pragma unroll
@@ -442,9 +455,9 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
                         }
                 const float inv = 1.0f / (sqrtf(G0 * G0 + G1 * G1 + G2 * G2) + eps);
                 float *n = &sm.n[it % 3][0][0];
-                n[i] = G0 * inv;
-                n[NGEO + i] = G1 * inv;
-                n[2 * NGEO + i] = G2 * inv;
+                n[gi] = G0 * inv;
+                n[NGEO + gi] = G1 * inv;
+                n[2 * NGEO + gi] = G2 * inv;
                 const int ssx = gxl - 1, ssy = gyl - 1;
                 if (ssx >= 0 && ssx < SX && ssy >= 0 && ssy < SY) {
                     float *Gs = &sm.G[it % 3][0][0];
@@ -502,7 +515,7 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
                     const float Hxy = tr3_m0(Xm[5], XB[5], XA[5]);
                     const float drho = m00.m0;
                     const float jx = m10.m0, jy = m01.m0, jz = m00.m1;
-                    const float inv = 1.0f / (1.0f + drho);
+                    const float inv = recip(1.0f + drho);
                     float m[10];
                     m[0] = drho;
                     m[1] = jx * inv;
