@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 BYTES_PER_NODE = {"fp32": 88, "fp16": 48, "bf16": 48, "fp16q": 64}
+BYTES_PER_NODE_1C = {"fp32": 80, "fp16": 40, "bf16": 40, "fp16q": 56}  # one component: no phase plane
 # HBM traffic of the fused step from rocprofv3 counters, valid while the kernel
 # sources hash to the value recorded next to the figures
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_step_jet128_traffic.txt")
@@ -41,10 +42,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="jet128", choices=["jet128", "jet512", "droplet32"])
+    ap.add_argument("--workload", default="jet128", choices=["jet128", "jet512", "droplet32", "tgv256"])
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16", "fp16q"])
     ap.add_argument("--variants", default="fp16,bf16,fp16q", help="other storage types timed on the same workload")
     ap.add_argument("--serve", type=int, default=256, help="requests in the serving stream (0 = skip)")
+    ap.add_argument("--single", type=int, default=1, help="also time the one-component Taylor-Green vortex (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-oracle sample budget (0 = skip)")
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the copy-kernel ceiling probe (0 = skip)")
     ap.add_argument("--kernel", default="fused", choices=["fused", "gather"])
@@ -62,10 +64,15 @@ def workload_state(name):
     p = w["params"]
     if w["init"] == "droplet":
         return p, inputs.droplet(p["nx"], 8.0, p["width"], noise_amp=1e-3, seed=1)
+    if w["init"] == "taylor_green":
+        return p, inputs.taylor_green(p["nx"])
     return p, None
 
 
 def describe(name, p):
+    if name.startswith("tgv"):
+        return {"workload": "Taylor-Green vortex %d^3, one component, U0=0.05, Re=1600, periodic" % p["nx"],
+                "nodes": p["nx"] * p["ny"] * p["nz"]}
     if name.startswith("jet"):
         d, u = p["inlet_d"], p["inlet_u"]
         return {"workload": "round jet %dx%dx%d, D=%g, U=%g, Re=%g, We=%g, inlet noise %g, outflow at z max, "
@@ -116,8 +123,9 @@ def run_lattice(name, storage, steps, warmup, kernel="fused"):
         # quiescent: rho = 1, u = 0, P = 0, phi = 0 is the all-zero raw state
         sim.set_state_raw(np.zeros(sim.state_bytes, np.uint8), step=0)
     else:
+        one = p.get("components", 2) == 1
         sim.set_state(rho_dev=np.asarray(st["rho"] - 1.0, np.float32), u=np.asarray(st["u"], np.float32),
-                      P=np.asarray(st["P"], np.float32), phi=np.asarray(st["phi"], np.float32))
+                      P=np.asarray(st["P"], np.float32), phi=None if one else np.asarray(st["phi"], np.float32))
     log("%s %s, warmup %d" % (name, storage, warmup))
     sim.step(warmup)
     sim.sync()
@@ -131,7 +139,7 @@ def run_lattice(name, storage, steps, warmup, kernel="fused"):
     diag = sim.diagnostics()
     sim.close()
     T = t1 - t0
-    bpn = BYTES_PER_NODE[storage]
+    bpn = (BYTES_PER_NODE_1C if p.get("components", 2) == 1 else BYTES_PER_NODE)[storage]
     achieved = bpn * nodes / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else None
     log("%s %s: %.3f s for %d steps, kernel %.4f ms/launch, finite=%s" % (name, storage, T, steps, kernel_ms,
                                                                           diag["finite"]))
@@ -212,6 +220,14 @@ def main():
                        "roofline_frac": r["achieved"] / HBM_PEAK_GBS if r["achieved"] else None,
                        "bytes_per_node": r["bpn"], "speedup_vs_%s" % a.storage: r["glups"] / m["glups"],
                        "finite": r["finite"]}
+    single = None
+    if a.single and a.workload != "tgv256":
+        r = run_lattice("tgv256", "fp32", max(1, a.steps // 2), max(1, a.warmup // 2), a.kernel)
+        single = {"workload": describe("tgv256", r["p"])["workload"], "nodes": r["nodes"], "value": r["glups"],
+                  "unit": "GLUPS", "kernel_ms": r["kernel_ms"], "bytes_per_node": r["bpn"],
+                  "roofline_frac": r["achieved"] / HBM_PEAK_GBS if r["achieved"] else None,
+                  "frac_of_copy_ceiling": r["achieved"] / copy["gbps"] if (copy and r["achieved"]) else None,
+                  "finite": r["finite"]}
     rec = {
         "metric": "GLUPS (lattice-node updates per second / 1e9) and fraction of the HBM roofline",
         "value": m["glups"],
@@ -234,6 +250,7 @@ def main():
                      "copy_ceiling": copy["gbps"] if copy else None,
                      "frac_of_copy_ceiling": achieved / copy["gbps"] if (copy and achieved) else None},
         "storage_variants": variants,
+        "single_component": single,
         "serving": serving(a.serve) if a.serve > 0 else None,
         "cpu_baseline": cpu_baseline(p, m["st"], a.cpu_seconds),
     }

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define TSLB_ABI_VERSION 1
+#define TSLB_ABI_VERSION 2
 
 enum {
     TSLB_OK = 0,
@@ -102,9 +102,14 @@ typedef struct tslb_params {
     void *device_buffer;     /* optional caller-owned device allocation for the state */
     size_t device_buffer_bytes;
     void *stream;            /* optional hipStream_t; NULL = the context creates its own */
+    int32_t components;      /* 2 (default): two components, the phase field of Eqs. 20-24 coupled
+                                through surface tension; 1: a single component, the high-order
+                                regularised hydrodynamics alone (no phase plane in the state,
+                                F = 0; sigma, width, gamma and eps are ignored, tslb_phase returns
+                                zeros and the phase sum is 0) */
 } tslb_params;
 
-/* Fill *p with defaults: periodic 32^3, nu = 0.1, sigma = 0, W = 3, FP32. */
+/* Fill *p with defaults: periodic 32^3, nu = 0.1, sigma = 0, W = 3, FP32, two components. */
 void tslb_params_init(tslb_params *p);
 
 /* sizeof(tslb_params) as compiled into the library (binding layout check). */

@@ -69,6 +69,7 @@ bool validate(const tslb_params *p, std::string &why) {
     if (!(p->sigma >= 0.0) || !std::isfinite(p->sigma)) { why = "sigma must be >= 0"; return false; }
     if (!(p->width > 0.0) || !std::isfinite(p->width)) { why = "width must be positive"; return false; }
     if (p->storage < TSLB_STORE_FP32 || p->storage > TSLB_STORE_FP16Q) { why = "unknown storage"; return false; }
+    if (p->components != 1 && p->components != 2) { why = "components must be 1 or 2"; return false; }
     if (p->check_interval < 0) { why = "check_interval must be >= 0"; return false; }
     if (p->bc[4] == TSLB_BC_INLET && !(p->inlet_d > 0.0)) { why = "inlet_d must be positive"; return false; }
     return true;
@@ -124,6 +125,7 @@ void tslb_params_init(tslb_params *p) {
     p->gamma = 0.0;
     p->eps = -1.0;
     p->storage = TSLB_STORE_FP32;
+    p->components = 2;
     p->u_scale = 0.0;
 }
 
@@ -133,7 +135,7 @@ size_t tslb_required_bytes(const tslb_params *p) {
     std::string why;
     if (!validate(p, why)) return 0;
     long long N = (long long)p->nx * p->ny * p->nz;
-    return 2 * state_buffer_bytes(N, p->storage);
+    return 2 * state_buffer_bytes(N, p->storage, p->components == 2);
 }
 
 int tslb_create(const tslb_params *p, tslb_ctx **out) {
@@ -147,6 +149,7 @@ int tslb_create(const tslb_params *p, tslb_ctx **out) {
     if (!c) return fail(nullptr, TSLB_E_NOMEM, "host allocation failed");
     c->p = *p;
     c->storage = p->storage;
+    c->phase = p->components == 2;
     {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
@@ -160,7 +163,7 @@ int tslb_create(const tslb_params *p, tslb_ctx **out) {
     c->has_boundary = !(g.per[0] && g.per[1] && g.per[2]);
     Phys &ph = c->phys;
     ph.omega = (float)(1.0 / (3.0 * p->nu + 0.5));
-    ph.sigma = (float)p->sigma;
+    ph.sigma = c->phase ? (float)p->sigma : 0.0f;
     ph.gamma = (float)(p->gamma > 0.0 ? p->gamma : 2.0 / p->width);
     ph.eps = (float)(p->eps >= 0.0 ? p->eps : 1e-4);
     ph.width = (float)p->width;
@@ -175,7 +178,7 @@ int tslb_create(const tslb_params *p, tslb_ctx **out) {
     c->scales.s2 = (float)(U * U);
     c->scales.inv_s1 = (float)(1.0 / U);
     c->scales.inv_s2 = (float)(1.0 / (U * U));
-    c->buffer_bytes = state_buffer_bytes(g.N, c->storage);
+    c->buffer_bytes = state_buffer_bytes(g.N, c->storage, c->phase);
     size_t need = 2 * c->buffer_bytes;
     if (p->device_buffer) {
         if (p->device_buffer_bytes < need) {
@@ -200,7 +203,7 @@ int tslb_create(const tslb_params *p, tslb_ctx **out) {
     for (int b = 0; b < 2; ++b) {
         char *base = (char *)c->base + b * c->buffer_bytes;
         c->buf[b].mom = base;
-        c->buf[b].phi = (int32_t *)(base + mom_bytes);
+        c->buf[b].phi = c->phase ? (int32_t *)(base + mom_bytes) : nullptr;
     }
     if (p->stream) {
         c->stream = (hipStream_t)p->stream;
@@ -232,7 +235,7 @@ int tslb_set_state(tslb_ctx *c, const float *rho_dev, const float *u, const floa
                    int64_t step) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
     NOT_IN_GROUP(c);
-    if (!rho_dev || !u || !pi_neq || !phi) return fail(c, TSLB_E_INVAL, "every field is required");
+    if (!rho_dev || !u || !pi_neq || (!phi && c->phase)) return fail(c, TSLB_E_INVAL, "every field is required");
     if (step < 0) return fail(c, TSLB_E_INVAL, "step must be >= 0");
     int rc = ensure_planes(c);
     if (rc) return rc;
@@ -241,7 +244,7 @@ int tslb_set_state(tslb_ctx *c, const float *rho_dev, const float *u, const floa
     HIP_TRY(c, hipMemcpyAsync(st, rho_dev, N * 4, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpy2DAsync(st + ld, ld * 4, u, N * 4, N * 4, 3, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpy2DAsync(st + 4 * ld, ld * 4, pi_neq, N * 4, N * 4, 6, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(st + 10 * ld, phi, N * 4, hipMemcpyHostToDevice, c->stream));
+    if (c->phase) HIP_TRY(c, hipMemcpyAsync(st + 10 * ld, phi, N * 4, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, launch_set_state(c, st, c->scratch.geo, c->buf[c->cur], c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->step = step;
@@ -337,6 +340,10 @@ int tslb_phase(tslb_ctx *c, float *phi) {
     int rc = fill_boundary_now(c);
     if (rc) return rc;
     const size_t N = (size_t)c->geo.N;
+    if (!c->phase) {  // a single component has no phase field
+        std::fill(phi, phi + N, 0.0f);
+        return TSLB_OK;
+    }
     std::vector<int32_t> fixed(N);
     HIP_TRY(c, hipMemcpyAsync(fixed.data(), c->buf[c->cur].phi, N * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));

@@ -45,6 +45,8 @@ struct tslb_group {
 namespace {
 
 constexpr int kStorageTypes = 4;  // TSLB_STORE_FP32 .. TSLB_STORE_FP16Q
+constexpr int kClasses = 2 * kStorageTypes;  // launch classes: storage type x component count
+int class_of(const tslb_ctx *c) { return 2 * c->storage + (c->phase ? 1 : 0); }
 
 int gfail(tslb_group *g, int code, const std::string &msg) {
     if (g)
@@ -116,8 +118,8 @@ int tslb_group_create(size_t hbm_budget_bytes, int32_t max_domains, void *stream
     g->budget = hbm_budget_bytes;
     g->max_domains = max_domains;
     hipError_t e = hipGetDevice(&g->device);
-    // the storage types share one table of kStorageTypes * max_domains records per slot
-    const size_t tab = kStorageTypes * (size_t)max_domains * sizeof(FusedDomain);
+    // every member has one record per launch: max_domains records per slot
+    const size_t tab = (size_t)max_domains * sizeof(FusedDomain);
     for (int s = 0; e == hipSuccess && s < tslb_group::kRing; ++s) {
         e = hipHostMalloc((void **)&g->h_tab[s], tab, hipHostMallocDefault);
         if (e == hipSuccess) e = hipMalloc((void **)&g->d_tab[s], tab);
@@ -215,23 +217,26 @@ int tslb_group_poll(tslb_group *g, tslb_ctx **done, int32_t cap, int32_t *ndone)
     const bool long_chunks = long_work >= cus;
     FusedDomain *h = g->h_tab[slot];
     int nrec = 0;
-    int first[kStorageTypes] = {}, count[kStorageTypes] = {}, work[kStorageTypes] = {};
-    for (int st = 0; st < kStorageTypes; ++st) {
-        first[st] = nrec;
+    // one launch per class (storage type, component count) present
+    int first[kClasses] = {}, count[kClasses] = {}, work[kClasses] = {};
+    for (int cl = 0; cl < kClasses; ++cl) {
+        first[cl] = nrec;
         for (tslb_group::Member &m : g->members) {
             tslb_ctx *c = m.ctx;
-            if (m.remaining <= 0 || c->storage != st) continue;
-            h[nrec] = fused_domain(c, c->buf[c->cur], c->buf[c->cur ^ 1], c->step + 1, work[st],
+            if (m.remaining <= 0 || class_of(c) != cl) continue;
+            h[nrec] = fused_domain(c, c->buf[c->cur], c->buf[c->cur ^ 1], c->step + 1, work[cl],
                                    long_chunks ? std::min(64, c->geo.nz) : 0);
-            work[st] += h[nrec].work_count;
+            work[cl] += h[nrec].work_count;
             ++nrec;
-            ++count[st];
+            ++count[cl];
         }
     }
     GHIP_TRY(g, hipMemcpyAsync(g->d_tab[slot], h, (size_t)nrec * sizeof(FusedDomain), hipMemcpyHostToDevice,
                                g->stream));
-    for (int st = 0; st < kStorageTypes; ++st)
-        if (count[st]) GHIP_TRY(g, launch_step_fused_multi(g->d_tab[slot] + first[st], count[st], work[st], st, g->stream));
+    for (int cl = 0; cl < kClasses; ++cl)
+        if (count[cl])
+            GHIP_TRY(g, launch_step_fused_multi(g->d_tab[slot] + first[cl], count[cl], work[cl], cl >> 1,
+                                                (cl & 1) != 0, g->stream));
     GHIP_TRY(g, hipEventRecord(g->ev[slot], g->stream));
     g->slot_launch[slot] = id;
     g->launches = id + 1;

@@ -55,6 +55,7 @@ struct tslb_ctx {
     tslb::Scales scales;
     int storage;
     bool has_boundary;
+    bool phase = true;    // two components (a phase-field plane); false: single component
     size_t plane_bytes;   // bytes of one moment plane (storage type)
     size_t buffer_bytes;  // bytes of one state buffer
     void *base = nullptr; // both buffers
@@ -82,7 +83,7 @@ void set_thread_error(const std::string &msg);
 void group_detach(tslb_group *g, tslb_ctx *c);
 
 size_t plane_elems(long long N);
-size_t state_buffer_bytes(long long N, int storage);
+size_t state_buffer_bytes(long long N, int storage, bool phase);
 
 // Launchers (all asynchronous on `s`); each returns the hipError_t of the launch.
 hipError_t launch_geometry(const tslb_ctx *c, const int32_t *phi, float *geo_planes, hipStream_t s);
@@ -100,8 +101,10 @@ FusedDomain fused_domain(const tslb_ctx *c, StateView in, StateView out, int64_t
                          int lz = 0);
 // Work items of one fused step of ctx c with z chunk lz.
 int fused_work_items(const tslb_ctx *c, int lz);
-// One fused step of every domain of a device table (all of one storage type).
-hipError_t launch_step_fused_multi(const FusedDomain *doms, int ndom, int total_work, int storage, hipStream_t s);
+// One fused step of every domain of a device table (all of one storage type and
+// component count).
+hipError_t launch_step_fused_multi(const FusedDomain *doms, int ndom, int total_work, int storage, bool phase,
+                                   hipStream_t s);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
 hipError_t launch_diagnostics(const tslb_ctx *c, StateView st, const Scratch &sc, hipStream_t s);
 size_t diagnostics_blocks(const tslb_ctx *c);

@@ -10,9 +10,9 @@ constexpr int kBlock = 256;
 
 size_t plane_elems(long long N) { return (size_t)((N + 63) / 64 * 64); }
 
-size_t state_buffer_bytes(long long N, int storage) {
+size_t state_buffer_bytes(long long N, int storage, bool phase) {
     size_t ld = plane_elems(N);
-    return moment_bytes(storage, (long long)ld) + ld * 4;
+    return moment_bytes(storage, (long long)ld) + (phase ? ld * 4 : 0);
 }
 
 __device__ __forceinline__ void decompose(const Geo &g, long long id, int &x, int &y, int &z) {
@@ -51,6 +51,11 @@ __global__ __launch_bounds__(kBlock) void k_gradient(Geo g, const int32_t *__res
                                                      float eps) {
     long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= g.N) return;
+    if (!phi) {  // single component: no interface, G = n = 0
+#pragma unroll
+        for (int k = 0; k < 6; ++k) geo[k * g.ld + id] = 0.f;
+        return;
+    }
     int x, y, z;
     decompose(g, id, x, y, z);
     float G0 = 0.f, G1 = 0.f, G2 = 0.f;
@@ -120,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Geo g, float sigma, float *__r
 // the fixed-point phi already written into `out`.
 __global__ __launch_bounds__(kBlock) void k_stage_phi(Geo g, const float *__restrict__ stage, StateView out) {
     long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= g.N) return;
+    if (id >= g.N || !out.phi) return;
     out.phi[id] = phi_from_float(stage[10 * g.ld + id]);
 }
 
@@ -159,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_readout(Geo g, Scales sc, StateView 
     const int A[6] = {0, 1, 2, 0, 0, 1}, B[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
     for (int s = 0; s < 6; ++s) stage[(4 + s) * ld + id] = m[4 + s] + 0.25f * inv * F[A[s]] * F[B[s]];
-    stage[10 * ld + id] = phi_to_float(in.phi[id]);
+    stage[10 * ld + id] = in.phi ? phi_to_float(in.phi[id]) : 0.f;
 }
 
 // ---- boundary layers (Eqs. 9, 10) ----
@@ -190,10 +195,10 @@ __global__ __launch_bounds__(kBlock) void k_boundary(Geo g, Phys ph, Scales sc, 
     long long id = node_id(g, v[0], v[1], v[2]);
     float m[10];
     load_raw<ST>(st, g, sc, idF, m);
-    int32_t phi = st.phi[idF];
+    int32_t phi = st.phi ? st.phi[idF] : 0;
     apply_boundary_rule(ph, g, face, v[0], v[1], step, m, phi);
     store_raw<ST>(st, g, sc, id, m);
-    st.phi[id] = phi;
+    if (st.phi) st.phi[id] = phi;
 }
 
 // ---- diagnostics ----
@@ -215,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_diag_partial(Geo g, Scales sc, State
         float y0 = m[0] - c0, t0 = s0 + y0;
         c0 = (t0 - s0) - y0;
         s0 = t0;
-        sphi += st.phi[id];
+        if (st.phi) sphi += st.phi[id];
         float z = 0.f;
 #pragma unroll
         for (int p = 0; p < 10; ++p) z += 0.f * m[p];
@@ -336,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_step_gather(Geo g, Phys ph, Scales s
         if (cx * cy) acc[7] += (cx * cy) * df;
         if (cx * cz) acc[8] += (cx * cz) * df;
         if (cy * cz) acc[9] += (cy * cz) * df;
-        if (cx * cx + cy * cy + cz * cz <= 1) {
+        if (in.phi && cx * cx + cy * cy + cz * cz <= 1) {
             const int32_t ps = in.phi[s];
             const int32_t base = (ps + 4) >> 3;
             if (cx | cy | cz) {
@@ -369,7 +374,7 @@ __global__ __launch_bounds__(kBlock) void k_step_gather(Geo g, Phys ph, Scales s
     m[8] = acc[8] - acc[1] * acc[3] * inv;
     m[9] = acc[9] - acc[2] * acc[3] * inv;
     store_raw<ST>(out, g, sc, id, m);
-    out.phi[id] = phin;
+    if (out.phi) out.phi[id] = phin;
 }
 
 // ---- launchers ----

@@ -46,16 +46,22 @@ constexpr int GX = TX + 4, GY = TY + 4, NGEO = GX * GY;   // geometry: 36 x 20
 constexpr int PX = TX + 6, PY = TY + 6, NPHI = PX * PY;   // phase field: 38 x 22
 constexpr int NDST = TX * TY;                              // 512
 constexpr int NT = 640;                                    // threads per workgroup
-constexpr int NXCH = 35;                                   // exchange slots per source
+constexpr int NXCH = 35;                                   // exchange slots per source (two components)
+constexpr int NXCH1 = 28;                                  // exchange slots per source (one component)
 
 static_assert(NSRC <= NT && NDST <= NSRC, "tile does not fit the workgroup");
 static_assert(NPHI <= 2 * NT && NGEO <= 2 * NT, "staging loops assume two items per thread");
 
-struct Smem {
+// LDS of a workgroup: PH = two components (with the phase field), else one.
+template <bool PH> struct Smem;
+template <> struct Smem<true> {
     int32_t phi[4][NPHI];      // fixed-point phase field, ring of 4 planes
     float n[3][3][NGEO];       // unit normal, ring of 3 planes
     float G[3][3][NSRC];       // gradient on the source region, ring of 3 planes
     float xch[NXCH][NSRC];     // populations crossing columns
+};
+template <> struct Smem<false> {
+    float xch[NXCH1][NSRC];    // populations crossing columns
 };
 
 // 1-D three-point transform of (a_-, a_0, a_+) with weights (1/6, 2/3, 1/6):
@@ -136,10 +142,14 @@ __device__ __forceinline__ int xcd_work_item(int b, int nb) {
 }
 
 // One work item (a tile and a z chunk) of one lattice.
-template <int ST>
-__device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &ph, const Scales &sc,
+template <int ST, bool PH>
+__device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phys &ph, const Scales &sc,
                                            const StateView &in, const StateView &out, int lz, int tiles_x,
                                            int tiles_y, unsigned long long step_next, int w) {
+    // exchange slots: 0-23 the x/y-crossing populations of the three z groups,
+    // then (two components) 24-27 phase +-x, +-y; rho'; phase rest, +z, -z;
+    // and the three populations of velocity (0, 0, c_z)
+    constexpr int kRho = PH ? 28 : 24, kCen = PH ? 32 : 25;
     const int tile = w % (tiles_x * tiles_y);
     const int chunk = w / (tiles_x * tiles_y);
     // The tile owns columns [xo, xo + TX) x [yo, yo + TY); its origin (x0, y0) is
@@ -243,7 +253,7 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
 
     const int nit = (z1 - z0) + 6;
     // prologue: phase planes z0 - 3 and z0 - 2 staged (slots 0, 1); z0 - 1 prefetched
-    {
+    if constexpr (PH) {
         int32_t v[2] = {0, 0};
         load_phi(z0 - 3, v);
 #pragma unroll
@@ -281,43 +291,47 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
         //     + sum_cx w1(cx) (n_y(x+cx, y+1) - n_y(x+cx, y-1)),
         //   E = sum_{cx,cy} w1(cx) w1(cy) n_z(x+cx, y+cy),
         // so each source keeps C and E of three planes in registers.
-        if (it >= 2 && is_src) {
-            const float *nq = &sm.n[(it + 2) % 3][0][0];  // plane q, written one iteration ago
-            const float *nyq = nq + NGEO, *nzq = nq + 2 * NGEO;
-            const int c = (sy + 1) * GX + (sx + 1);  // centre in the geometry region
-            const float Cx = w1sum(nq[c - GX + 1] - nq[c - GX - 1], nq[c + 1] - nq[c - 1], nq[c + GX + 1] - nq[c + GX - 1]);
-            const float Cy = w1sum(nyq[c + GX - 1] - nyq[c - GX - 1], nyq[c + GX] - nyq[c - GX],
-                                   nyq[c + GX + 1] - nyq[c - GX + 1]);
-            const float E = w1sum(w1sum(nzq[c - GX - 1], nzq[c - GX], nzq[c - GX + 1]),
-                                  w1sum(nzq[c - 1], nzq[c], nzq[c + 1]),
-                                  w1sum(nzq[c + GX - 1], nzq[c + GX], nzq[c + GX + 1]));
-            cA = cB;
-            cB = cC;
-            cC = Cx + Cy;
-            eA = eB;
-            eB = eC;
-            eC = E;
+        if constexpr (PH) {
+            if (it >= 2 && is_src) {
+                const float *nq = &sm.n[(it + 2) % 3][0][0];  // plane q, written one iteration ago
+                const float *nyq = nq + NGEO, *nzq = nq + 2 * NGEO;
+                const int c = (sy + 1) * GX + (sx + 1);  // centre in the geometry region
+                const float Cx = w1sum(nq[c - GX + 1] - nq[c - GX - 1], nq[c + 1] - nq[c - 1], nq[c + GX + 1] - nq[c + GX - 1]);
+                const float Cy = w1sum(nyq[c + GX - 1] - nyq[c - GX - 1], nyq[c + GX] - nyq[c - GX],
+                                       nyq[c + GX + 1] - nyq[c - GX + 1]);
+                const float E = w1sum(w1sum(nzq[c - GX - 1], nzq[c - GX], nzq[c - GX + 1]),
+                                      w1sum(nzq[c - 1], nzq[c], nzq[c + 1]),
+                                      w1sum(nzq[c + GX - 1], nzq[c + GX], nzq[c + GX + 1]));
+                cA = cB;
+                cB = cC;
+                cC = Cx + Cy;
+                eA = eB;
+                eB = eC;
+                eC = E;
+            }
         }
 
         if (it >= 4) {
             // ---- S3: kappa and F at the source (plane r = q - 1) ----
             float F0 = 0.f, F1 = 0.f, F2 = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
             int32_t phis = 0;
-            if (is_src) {
-                const float kap = 0.5f * (w1sum(cA, cB, cC) + (eC - eA));
-                const int zr = r;
-                const bool bnd = src_bnd_xy || (!g.per[2] && (zr <= 0 || zr >= g.nz - 1));
-                const float a = bnd ? 0.f : -sigma * kap;
-                const float *Gs = &sm.G[(it + 1) % 3][0][0];  // plane r
-                F0 = a * Gs[sidx];
-                F1 = a * Gs[NSRC + sidx];
-                F2 = a * Gs[2 * NSRC + sidx];
-                const float *nr = &sm.n[(it + 1) % 3][0][0];  // plane r
-                const int c = (sy + 1) * GX + (sx + 1);
-                n0 = nr[c];
-                n1 = nr[NGEO + c];
-                n2 = nr[2 * NGEO + c];
-                phis = sm.phi[(it - 2) & 3][(sy + 2) * PX + (sx + 2)];
+            if constexpr (PH) {
+                if (is_src) {
+                    const float kap = 0.5f * (w1sum(cA, cB, cC) + (eC - eA));
+                    const int zr = r;
+                    const bool bnd = src_bnd_xy || (!g.per[2] && (zr <= 0 || zr >= g.nz - 1));
+                    const float a = bnd ? 0.f : -sigma * kap;
+                    const float *Gs = &sm.G[(it + 1) % 3][0][0];  // plane r
+                    F0 = a * Gs[sidx];
+                    F1 = a * Gs[NSRC + sidx];
+                    F2 = a * Gs[2 * NSRC + sidx];
+                    const float *nr = &sm.n[(it + 1) % 3][0][0];  // plane r
+                    const int c = (sy + 1) * GX + (sx + 1);
+                    n0 = nr[c];
+                    n1 = nr[NGEO + c];
+                    n2 = nr[2 * NGEO + c];
+                    phis = sm.phi[(it - 2) & 3][(sy + 2) * PX + (sx + 2)];
+                }
             }
 
             // ---- S4: post-collision populations of the source ----
@@ -385,15 +399,17 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
                         tp[k] = mid + T1[iy];
                     }
                 }
-                // phase: base to every axis neighbour, +-a_e along +-e, phi - 6 base stays
-                const float phif = phi_to_float(phis);
-                const float omphi = (float)(kPhiOne - phis) * kPhiUlp;
-                const float gph = gamma * omphi;
-                const float h8 = 0.125f * phif * kPhiInvUlp;
-                base = (phis + 4) >> 3;
-                ax = __float2int_rn(h8 * fmaf(4.0f, u0, gph * n0));
-                ay = __float2int_rn(h8 * fmaf(4.0f, u1, gph * n1));
-                az = __float2int_rn(h8 * fmaf(4.0f, u2, gph * n2));
+                if constexpr (PH) {
+                    // phase: base to every axis neighbour, +-a_e along +-e, phi - 6 base stays
+                    const float phif = phi_to_float(phis);
+                    const float omphi = (float)(kPhiOne - phis) * kPhiUlp;
+                    const float gph = gamma * omphi;
+                    const float h8 = 0.125f * phif * kPhiInvUlp;
+                    base = (phis + 4) >> 3;
+                    ax = __float2int_rn(h8 * fmaf(4.0f, u0, gph * n0));
+                    ay = __float2int_rn(h8 * fmaf(4.0f, u1, gph * n1));
+                    az = __float2int_rn(h8 * fmaf(4.0f, u2, gph * n2));
+                }
 
                 // ---- S5a: publish what crosses columns ----
 #pragma unroll
@@ -407,22 +423,24 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
                         sm.xch[8 + s][sidx] = t0[k];
                         sm.xch[16 + s][sidx] = tp[k];
                     }
-                sm.xch[24][sidx] = __int_as_float(base + ax);  // +x
-                sm.xch[25][sidx] = __int_as_float(base - ax);  // -x
-                sm.xch[26][sidx] = __int_as_float(base + ay);  // +y
-                sm.xch[27][sidx] = __int_as_float(base - ay);  // -y
-                sm.xch[28][sidx] = rp;
-                sm.xch[29][sidx] = __int_as_float(phis - 6 * base);  // rest
-                sm.xch[30][sidx] = __int_as_float(base + az);        // +z
-                sm.xch[31][sidx] = __int_as_float(base - az);        // -z
-                sm.xch[32][sidx] = tm[4];
-                sm.xch[33][sidx] = t0[4];
-                sm.xch[34][sidx] = tp[4];
+                if constexpr (PH) {
+                    sm.xch[24][sidx] = __int_as_float(base + ax);        // +x
+                    sm.xch[25][sidx] = __int_as_float(base - ax);        // -x
+                    sm.xch[26][sidx] = __int_as_float(base + ay);        // +y
+                    sm.xch[27][sidx] = __int_as_float(base - ay);        // -y
+                    sm.xch[29][sidx] = __int_as_float(phis - 6 * base);  // rest
+                    sm.xch[30][sidx] = __int_as_float(base + az);        // +z
+                    sm.xch[31][sidx] = __int_as_float(base - az);        // -z
+                }
+                sm.xch[kRho][sidx] = rp;
+                sm.xch[kCen][sidx] = tm[4];
+                sm.xch[kCen + 1][sidx] = t0[4];
+                sm.xch[kCen + 2][sidx] = tp[4];
             }
         }
 
         // ---- S2: G and n of plane p from phi planes p-1, p, p+1 (slots it-1, it, it+1) ----
-        if (it >= 1 && it + 2 <= nit) {
+        if constexpr (PH) if (it >= 1 && it + 2 <= nit) {
             const int32_t *pm = sm.phi[(it + 3) & 3], *p0 = sm.phi[it & 3], *pp = sm.phi[(it + 1) & 3];
             for (int k = 0; k < 2; ++k) {
                 const int i = geo_item[k];
@@ -475,10 +493,10 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
             // ---- S5b/S6: gather at the destination and finish plane r - 1 ----
             if (is_dst) {
                 float gm[9], g0[9], gp[9];
-                const float rp_ref = sm.xch[28][fidx];
-                gm[4] = sm.xch[32][fidx];
-                g0[4] = sm.xch[33][fidx];
-                gp[4] = sm.xch[34][fidx];
+                const float rp_ref = sm.xch[kRho][fidx];
+                gm[4] = sm.xch[kCen][fidx];
+                g0[4] = sm.xch[kCen + 1][fidx];
+                gp[4] = sm.xch[kCen + 2][fidx];
 #pragma unroll
                 for (int cy = -1; cy <= 1; ++cy)
 #pragma unroll
@@ -487,7 +505,7 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
                         const int k = (cx + 1) + 3 * (cy + 1);
                         const int s = xy_slot(cx, cy);
                         const int src = fidx - cy * SX - cx;
-                        const float drp = sm.xch[28][src] - rp_ref;
+                        const float drp = sm.xch[kRho][src] - rp_ref;
                         gm[k] = sm.xch[s][src] + drp;
                         g0[k] = sm.xch[8 + s][src] + drp;
                         gp[k] = sm.xch[16 + s][src] + drp;
@@ -499,11 +517,14 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
                 Xm[0] += rp_ref;
                 X0[0] += rp_ref;
                 Xp[0] += rp_ref;
-                const int32_t pin = __float_as_int(sm.xch[24][fidx - 1]) + __float_as_int(sm.xch[25][fidx + 1]) +
-                                    __float_as_int(sm.xch[26][fidx - SX]) + __float_as_int(sm.xch[27][fidx + SX]);
-                const int32_t prest = __float_as_int(sm.xch[29][fidx]);
-                const int32_t pup = __float_as_int(sm.xch[30][fidx]);
-                const int32_t pdown = __float_as_int(sm.xch[31][fidx]);
+                int32_t pin = 0, prest = 0, pup = 0, pdown = 0;
+                if constexpr (PH) {
+                    pin = __float_as_int(sm.xch[24][fidx - 1]) + __float_as_int(sm.xch[25][fidx + 1]) +
+                          __float_as_int(sm.xch[26][fidx - SX]) + __float_as_int(sm.xch[27][fidx + SX]);
+                    prest = __float_as_int(sm.xch[29][fidx]);
+                    pup = __float_as_int(sm.xch[30][fidx]);
+                    pdown = __float_as_int(sm.xch[31][fidx]);
+                }
                 // destination plane r - 1: X(-1) from source plane r, X(0) = XB, X(+1) = XA
                 const int zd = r - 1;
                 if (owned && zd >= z0 && zd < z1 && (g.per[2] || (zd > 0 && zd < g.nz - 1))) {
@@ -541,7 +562,7 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
                         const long long ib = (long long)gxs + (long long)g.nx * gys + plane * zb;
 #pragma unroll
                         for (int k = 0; k < 10; ++k) store_moment<ST>(out.mom, g.ld, k, ib, mb[k], sc);
-                        out.phi[ib] = pb;
+                        if constexpr (PH) out.phi[ib] = pb;
                     }
                     // the node itself: interior, or on an x/y wall (face rule of step t+1)
                     int32_t po = phin;
@@ -552,7 +573,7 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
                     const long long id = (long long)gxs + (long long)g.nx * gys + plane * zd;
 #pragma unroll
                     for (int k = 0; k < 10; ++k) store_moment<ST>(out.mom, g.ld, k, id, m[k], sc);
-                    out.phi[id] = po;
+                    if constexpr (PH) out.phi[id] = po;
                 }
                 // carry: plane r gets X(+1) = XC, X(0) = X0; plane r+1 gets X(+1) = Xp
 #pragma unroll
@@ -566,29 +587,31 @@ __device__ __forceinline__ void step_fused(Smem &sm, const Geo &g, const Phys &p
             }
         }
         // ---- S1: stage phi(p + 2) for the geometry of the next iteration ----
-        if (it + 3 <= nit) {
-#pragma unroll
-            for (int k = 0; k < 2; ++k)
-                if (phi_item[k] >= 0) sm.phi[(it + 2) & 3][phi_item[k]] = phi_next[k];
-            if (it + 4 <= nit) load_phi(p + 3, phi_next);
+        if constexpr (PH) {
+            if (it + 3 <= nit) {
+    #pragma unroll
+                for (int k = 0; k < 2; ++k)
+                    if (phi_item[k] >= 0) sm.phi[(it + 2) & 3][phi_item[k]] = phi_next[k];
+                if (it + 4 <= nit) load_phi(p + 3, phi_next);
+            }
         }
         __syncthreads();
     }
 }
 
 
-template <int ST>
+template <int ST, bool PH>
 __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, StateView in, StateView out, int lz,
                                                    int tiles_x, int tiles_y, unsigned long long step_next) {
-    __shared__ Smem sm;
-    step_fused<ST>(sm, g, ph, sc, in, out, lz, tiles_x, tiles_y, step_next, xcd_work_item(blockIdx.x, gridDim.x));
+    __shared__ Smem<PH> sm;
+    step_fused<ST, PH>(sm, g, ph, sc, in, out, lz, tiles_x, tiles_y, step_next, xcd_work_item(blockIdx.x, gridDim.x));
 }
 
 // Several lattices in one launch: the work items of domain k are
 // [work_begin, work_begin + tiles * chunks); domains are sorted by work_begin.
-template <int ST>
+template <int ST, bool PH>
 __global__ __launch_bounds__(NT) void k_step_fused_multi(const FusedDomain *__restrict__ doms, int ndom) {
-    __shared__ Smem sm;
+    __shared__ Smem<PH> sm;
     const int w = xcd_work_item(blockIdx.x, gridDim.x);
     int lo = 0, hi = ndom - 1;
     while (lo < hi) {
@@ -599,7 +622,7 @@ __global__ __launch_bounds__(NT) void k_step_fused_multi(const FusedDomain *__re
             hi = mid - 1;
     }
     const FusedDomain &d = doms[lo];
-    step_fused<ST>(sm, d.g, d.ph, d.sc, d.in, d.out, d.lz, d.tiles_x, d.tiles_y, d.step_next, w - d.work_begin);
+    step_fused<ST, PH>(sm, d.g, d.ph, d.sc, d.in, d.out, d.lz, d.tiles_x, d.tiles_y, d.step_next, w - d.work_begin);
 }
 
 }  // namespace fused
@@ -640,6 +663,24 @@ FusedDomain fused_domain(const tslb_ctx *c, StateView in, StateView out, int64_t
 }
 
 // Launch the fused step over the whole lattice.
+namespace {
+
+template <int ST, bool PH>
+void launch_one(unsigned blocks, hipStream_t s, const tslb_ctx *c, StateView in, StateView out, int lz, int tiles_x,
+                int tiles_y, unsigned long long sn) {
+    using namespace fused;
+    hipLaunchKernelGGL((k_step_fused<ST, PH>), dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in, out, lz,
+                       tiles_x, tiles_y, sn);
+}
+
+template <int ST, bool PH>
+void launch_multi(unsigned blocks, hipStream_t s, const FusedDomain *doms, int ndom) {
+    using namespace fused;
+    hipLaunchKernelGGL((k_step_fused_multi<ST, PH>), dim3(blocks), dim3(NT), 0, s, doms, ndom);
+}
+
+}  // namespace
+
 hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int lz, int64_t step_next,
                              hipStream_t s) {
     using namespace fused;
@@ -647,44 +688,45 @@ hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int
     const int chunks = (c->geo.nz + lz - 1) / lz;
     const unsigned blocks = (unsigned)tiles_x * tiles_y * chunks;
     const unsigned long long sn = (unsigned long long)step_next;
+#define TSLB_FUSED_CASE(ST)                                                                            \
+    case ST:                                                                                           \
+        if (c->phase)                                                                                  \
+            launch_one<ST, true>(blocks, s, c, in, out, lz, tiles_x, tiles_y, sn);                     \
+        else                                                                                           \
+            launch_one<ST, false>(blocks, s, c, in, out, lz, tiles_x, tiles_y, sn);                    \
+        break;
     switch (c->storage) {
-    case ST_FP32:
-        hipLaunchKernelGGL(k_step_fused<ST_FP32>, dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in, out,
-                           lz, tiles_x, tiles_y, sn);
-        break;
-    case ST_FP16:
-        hipLaunchKernelGGL(k_step_fused<ST_FP16>, dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in, out,
-                           lz, tiles_x, tiles_y, sn);
-        break;
-    case ST_BF16:
-        hipLaunchKernelGGL(k_step_fused<ST_BF16>, dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in, out,
-                           lz, tiles_x, tiles_y, sn);
-        break;
+        TSLB_FUSED_CASE(ST_FP32)
+        TSLB_FUSED_CASE(ST_FP16)
+        TSLB_FUSED_CASE(ST_BF16)
+        TSLB_FUSED_CASE(ST_FP16Q)
     default:
-        hipLaunchKernelGGL(k_step_fused<ST_FP16Q>, dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in,
-                           out, lz, tiles_x, tiles_y, sn);
-        break;
+        return hipErrorInvalidValue;
     }
+#undef TSLB_FUSED_CASE
     return hipGetLastError();
 }
 
-hipError_t launch_step_fused_multi(const FusedDomain *doms, int ndom, int total_work, int storage, hipStream_t s) {
-    using namespace fused;
+hipError_t launch_step_fused_multi(const FusedDomain *doms, int ndom, int total_work, int storage, bool phase,
+                                   hipStream_t s) {
     if (ndom <= 0 || total_work <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)total_work;
+#define TSLB_MULTI_CASE(ST)                                                                            \
+    case ST:                                                                                           \
+        if (phase)                                                                                     \
+            launch_multi<ST, true>(blocks, s, doms, ndom);                                             \
+        else                                                                                           \
+            launch_multi<ST, false>(blocks, s, doms, ndom);                                            \
+        break;
     switch (storage) {
-    case ST_FP32:
-        hipLaunchKernelGGL(k_step_fused_multi<ST_FP32>, dim3(total_work), dim3(NT), 0, s, doms, ndom);
-        break;
-    case ST_FP16:
-        hipLaunchKernelGGL(k_step_fused_multi<ST_FP16>, dim3(total_work), dim3(NT), 0, s, doms, ndom);
-        break;
-    case ST_BF16:
-        hipLaunchKernelGGL(k_step_fused_multi<ST_BF16>, dim3(total_work), dim3(NT), 0, s, doms, ndom);
-        break;
+        TSLB_MULTI_CASE(ST_FP32)
+        TSLB_MULTI_CASE(ST_FP16)
+        TSLB_MULTI_CASE(ST_BF16)
+        TSLB_MULTI_CASE(ST_FP16Q)
     default:
-        hipLaunchKernelGGL(k_step_fused_multi<ST_FP16Q>, dim3(total_work), dim3(NT), 0, s, doms, ndom);
-        break;
+        return hipErrorInvalidValue;
     }
+#undef TSLB_MULTI_CASE
     return hipGetLastError();
 }
 

@@ -84,6 +84,21 @@ def droplet(n, radius, width=3.0, noise_amp=1e-3, seed=1, stream=0, center=None,
     return {"rho": rho, "u": u, "P": np.zeros((6,) + phi.shape), "phi": phi}
 
 
+def taylor_green(n, u0=0.05):
+    """Periodic n^3 Taylor-Green vortex: with x_i = 2 pi i / n,
+    u = u0 sin x cos y cos z, v = -u0 cos x sin y cos z, w = 0,
+    rho = 1 + u0^2 / (16 c_s^2) (cos 2x + cos 2y)(cos 2z + 2), P = 0, phi = 0."""
+    k = 2.0 * np.pi / n
+    x, y, z = (np.arange(n, dtype=np.float64) * k for _ in range(3))
+    X, Y, Z = x[None, None, :], y[None, :, None], z[:, None, None]
+    sh = (n, n, n)
+    u = np.zeros((3,) + sh)
+    u[0] = u0 * np.sin(X) * np.cos(Y) * np.cos(Z)
+    u[1] = -u0 * np.cos(X) * np.sin(Y) * np.cos(Z)
+    rho = 1.0 + (u0 * u0 / (16.0 / 3.0)) * (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2.0)
+    return {"rho": np.broadcast_to(rho, sh).copy(), "u": u, "P": np.zeros((6,) + sh), "phi": np.zeros(sh)}
+
+
 # ---- workloads: plain parameter sets in lattice units ----
 
 def droplet_params(n=32, nu=0.01, sigma=0.01, width=3.0):
@@ -99,6 +114,9 @@ def jet_params(nx, ny, nz, d, u, re, we, width=3.0, noise=0.01, seed=2):
 
 
 WORKLOADS = {
+    # 256^3 periodic Taylor-Green vortex, one component, U0 = 0.05, Re = U0 (n / 2 pi) / nu = 1600
+    "tgv256": dict(params=dict(nx=256, ny=256, nz=256, nu=0.05 * (256 / (2 * np.pi)) / 1600.0, sigma=0.0, width=3.0,
+                               bc=(BC_PERIODIC,) * 6, components=1), steps=1000, init="taylor_green"),
     # 32^3 periodic droplet, R = 8, W = 3, nu = 0.01, sigma = 0.01, 200 steps
     "droplet32": dict(params=droplet_params(32), steps=200, init="droplet"),
     # 128x128x512 round jet, D = 20, U = 0.05, Re = 5000, We = 100, 2000 steps

@@ -16,7 +16,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtslb.so")
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSTABLE, E_STATE = 0, -1, -2, -3, -4, -5
 BC_PERIODIC, BC_FREESLIP, BC_INLET, BC_OUTFLOW, BC_NOSLIP = 0, 1, 2, 3, 4
@@ -56,6 +56,7 @@ class Params(ctypes.Structure):
         ("device_buffer", ctypes.c_void_p),
         ("device_buffer_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
+        ("components", ctypes.c_int32),
     ]
 
 
@@ -115,7 +116,7 @@ def load_library(path: str = LIB_PATH):
 
 def make_params(nx, ny, nz, nu, sigma=0.0, width=3.0, gamma=0.0, eps=-1.0, bc=(0,) * 6, inlet_u=0.0,
                 inlet_d=0.0, inlet_noise=0.0, seed=0, storage="fp32", u_scale=0.0, check_interval=0, device=0,
-                device_buffer=None, device_buffer_bytes=0, stream=None) -> Params:
+                device_buffer=None, device_buffer_bytes=0, stream=None, components=2) -> Params:
     lib = load_library()
     p = Params()
     lib.tslb_params_init(ctypes.byref(p))
@@ -132,6 +133,7 @@ def make_params(nx, ny, nz, nu, sigma=0.0, width=3.0, gamma=0.0, eps=-1.0, bc=(0
     p.device_buffer = device_buffer
     p.device_buffer_bytes = int(device_buffer_bytes)
     p.stream = stream
+    p.components = int(components)
     return p
 
 
@@ -188,12 +190,13 @@ class Simulation:
     def __exit__(self, *a):
         self.close()
 
-    def set_state(self, rho_dev, u, P, phi, step=0):
-        """Physical fields: rho_dev = rho - 1, u (3,...), P (6,...), phi."""
+    def set_state(self, rho_dev, u, P, phi=None, step=0):
+        """Physical fields: rho_dev = rho - 1, u (3,...), P (6,...), phi (None for one component)."""
         sh = self.shape
-        rho_dev, u, P, phi = _f32(rho_dev, sh), _f32(u, (3,) + sh), _f32(P, (6,) + sh), _f32(phi, sh)
+        rho_dev, u, P = _f32(rho_dev, sh), _f32(u, (3,) + sh), _f32(P, (6,) + sh)
+        phi_p = None if phi is None else _f32(phi, sh).ctypes.data_as(_F)
         self._check(self.lib.tslb_set_state(self.h, rho_dev.ctypes.data_as(_F), u.ctypes.data_as(_F),
-                                            P.ctypes.data_as(_F), phi.ctypes.data_as(_F), int(step)))
+                                            P.ctypes.data_as(_F), phi_p, int(step)))
 
     def step(self, n=1):
         self._check(self.lib.tslb_step(self.h, int(n)))

@@ -53,6 +53,9 @@ def test_defaults_and_required_bytes(lib):
     p.storage = tslb.STORE_FP16Q  # rho', ubar binary32 + six binary16 stress planes + phi
     assert lib.tslb_required_bytes(ctypes.byref(p)) == 2 * (4 * 4 + 6 * 2 + 4) * 32 ** 3
     p.storage = tslb.STORE_FP32
+    p.components = 1  # one component: the ten moment planes only
+    assert lib.tslb_required_bytes(ctypes.byref(p)) == 2 * 10 * 4 * 32 ** 3
+    p.components = 2
     p.nx = 33  # 33*32*32 = 33792 = 528 * 64: still aligned
     assert lib.tslb_required_bytes(ctypes.byref(p)) == 2 * 11 * 4 * 33792
     p.nx, p.ny, p.nz = 5, 3, 3  # 45 -> padded to 64
@@ -60,7 +63,7 @@ def test_defaults_and_required_bytes(lib):
 
 
 @pytest.mark.parametrize("field,value", [
-    ("nu", 0.0), ("nu", -1.0), ("width", 0.0), ("sigma", -1e-3), ("storage", 7), ("abi_version", 99),
+    ("nu", 0.0), ("nu", -1.0), ("width", 0.0), ("sigma", -1e-3), ("storage", 7), ("abi_version", 99), ("components", 3), ("components", 0),
     ("nx", 0), ("check_interval", -1)])
 def test_invalid_parameters_rejected_on_host(lib, field, value):
     p = tslb.Params()

@@ -310,3 +310,46 @@ def test_full_jet_step_matches_oracle_at_every_node():
     r1 = o.physical()
     o.close()
     assert_parity(g1, r1, TOL_FP32, "full-jet one step")
+
+
+def _hydro_parity(p, state, steps, label, step0=0):
+    """One-component GPU path against the oracle with sigma = 0: the phase field
+    then leaves the hydrodynamics alone (F = 0), so rho, u and P must agree."""
+    from oracle import Oracle
+    from paper_2403_15773_amd.tslb import Simulation
+    st = _f32(state)
+    with Simulation(**p, components=1) as s:
+        s.set_state(rho_dev=st["rho_dev"], u=st["u"], P=st["P"], phi=None, step=step0)
+        s.step(steps)
+        g = s.physical()
+        assert not g["phi"].any()
+    o = Oracle(p["nx"], p["ny"], p["nz"], nu=p["nu"], sigma=0.0, width=3.0, eps=EPS, bc=p["bc"],
+               inlet_u=p.get("inlet_u", 0.0), inlet_d=p.get("inlet_d", 0.0), inlet_noise=p.get("inlet_noise", 0.0),
+               seed=p.get("seed", 0))
+    o.set_physical(**_oracle_inputs(st), step=step0)
+    o.step(steps)
+    r = o.physical()
+    o.close()
+    errs = {k: v for k, v in field_errors(g, r).items() if k != "phi"}
+    _say(label + " " + " ".join("%s=%.2e" % (k, v[0]) for k, v in errs.items()))
+    bad = {k: v for k, v in errs.items() if not v[0] <= TOL_FP32}
+    assert not bad, bad
+
+
+def test_single_component_periodic_flow_parity():
+    """One component (no phase planes): a random flow on a 40 x 24 x 20 periodic box, 150 steps."""
+    _say("single component periodic 40x24x20, 150 steps")
+    nx, ny, nz = 40, 24, 20
+    st = inputs.quiescent(nx, ny, nz)
+    node = np.arange(nx * ny * nz, dtype=np.uint64)
+    st["u"] = 0.02 * np.stack([inputs.noise(5, 0, 0, node, a).reshape(nz, ny, nx) for a in range(3)])
+    st["rho"] = 1.0 + 0.005 * inputs.noise(5, 3, 0, node, 0).reshape(nz, ny, nx)
+    _hydro_parity(dict(nx=nx, ny=ny, nz=nz, nu=0.02, sigma=0.0, width=3.0, bc=(0,) * 6), st, 150,
+                  "single-component periodic")
+
+
+def test_single_component_jet_parity():
+    """One component: a 24 x 24 x 40 single-phase round jet (inlet, outflow, free-slip), 200 steps."""
+    _say("single component mini-jet 24x24x40, 200 steps")
+    p = inputs.jet_params(24, 24, 40, d=8.0, u=0.05, re=400.0, we=40.0, seed=9)
+    _hydro_parity(p, inputs.quiescent(24, 24, 40), 200, "single-component jet", step0=5)

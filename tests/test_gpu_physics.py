@@ -10,8 +10,9 @@ pytestmark = pytest.mark.gpu
 CS2 = 1.0 / 3.0
 
 
+@pytest.mark.parametrize("components", [2, 1])
 @pytest.mark.parametrize("nu", [0.01, 0.05])
-def test_taylor_green_shear_wave_viscosity(nu):
+def test_taylor_green_shear_wave_viscosity(nu, components):
     from paper_2403_15773_amd.tslb import Simulation
     L, A = 64, 1e-4
     k = 2 * np.pi / L
@@ -25,8 +26,8 @@ def test_taylor_green_shear_wave_viscosity(nu):
          "P": st["P"].astype(np.float32), "phi": st["phi"].astype(np.float32)}
     basis = np.sin(k * np.arange(L))
     ts, amps = [], []
-    with Simulation(nx=4, ny=L, nz=4, nu=nu, sigma=0.0) as s:
-        s.set_state(**f)
+    with Simulation(nx=4, ny=L, nz=4, nu=nu, sigma=0.0, components=components) as s:
+        s.set_state(**f) if components == 2 else s.set_state(f["rho_dev"], f["u"], f["P"])
         s.step(50)
         for _ in range(20):
             ux = s.moments()[1][0].astype(np.float64).mean(axis=(0, 2))
@@ -34,6 +35,6 @@ def test_taylor_green_shear_wave_viscosity(nu):
             amps.append(2.0 / L * (ux * basis).sum())
             s.step(50)
     rate = -np.polyfit(ts, np.log(amps), 1)[0]
-    print("[gpu-test] shear wave nu=%g: fitted %.6g, expected %.6g" % (nu, rate / k ** 2, CS2 * (1 / omega - 0.5)),
-          flush=True)
+    print("[gpu-test] shear wave nu=%g, %d component(s): fitted %.6g, expected %.6g" % (
+        nu, components, rate / k ** 2, CS2 * (1 / omega - 0.5)), flush=True)
     assert rate / k ** 2 == pytest.approx(CS2 * (1 / omega - 0.5), rel=0.01)

@@ -138,3 +138,37 @@ def test_small_serving_stream_completes():
     for rec in recs:
         assert rec.extra["step"] == rec.req.steps
         assert rec.req.arrival <= rec.admitted <= rec.done
+
+
+def test_group_mixes_one_and_two_component_lattices_bitwise():
+    """A group holding one- and two-component lattices of several storage types
+    launches one kernel per class; every member still ends bitwise equal to its
+    run alone."""
+    from paper_2403_15773_amd.tslb import Group, Simulation
+    _say("group mix of one- and two-component lattices")
+    reqs = _mix_requests()[:4]
+    cases = [(reqs[0], 1, "fp32"), (reqs[1], 2, "fp32"), (reqs[2], 1, "fp16q"), (reqs[3], 2, "fp16")]
+
+    def make(r, comps, storage):
+        p, f = serve.request_setup(r)
+        s = Simulation(**p, components=comps, storage=storage)
+        s.set_state(**f) if comps == 2 else s.set_state(f["rho_dev"], f["u"], f["P"])
+        return s
+
+    alone = []
+    for r, comps, storage in cases:
+        with make(r, comps, storage) as s:
+            s.step(r.steps)
+            alone.append(s.get_state_raw())
+    sims = [make(r, comps, storage) for r, comps, storage in cases]
+    with Group(hbm_budget_bytes=8 << 30, max_domains=8) as g:
+        for s, (r, _, _) in zip(sims, cases):
+            assert g.admit(s, r.steps)
+        left, polls = len(sims), 0
+        while left:
+            left -= len(g.poll())
+            polls += 1
+            assert polls < 10000
+    for s, a, (r, comps, storage) in zip(sims, alone, cases):
+        assert np.array_equal(s.get_state_raw(), a), "L=%d %d component(s) %s differs" % (r.L, comps, storage)
+        s.close()
