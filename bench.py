@@ -33,7 +33,8 @@ BYTES_PER_NODE = {"fp32": 88, "fp16": 48, "bf16": 48, "fp16q": 64}
 BYTES_PER_NODE_1C = {"fp32": 80, "fp16": 40, "bf16": 40, "fp16q": 56}  # one component: no phase plane
 # HBM traffic of the fused step from rocprofv3 counters, valid while the kernel
 # sources hash to the value recorded next to the figures
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_step_jet128_traffic.txt")
+TRAFFIC_FILES = {"jet128": os.path.join(ROOT, "profiles", "fused_step_jet128_traffic.txt"),
+                 "tgv256": os.path.join(ROOT, "profiles", "fused_step_tgv256_1c_traffic.txt")}
 KERNEL_SOURCES = ["paper_2403_15773_amd/csrc/tslb_step_fused.hip", "paper_2403_15773_amd/csrc/tslb_device.h"]
 
 
@@ -94,10 +95,11 @@ def sources_hash():
 def measured_traffic(workload, storage):
     """HBM bytes per fused-step launch from the committed counter summary, or
     None when it covers another workload or the kernel changed since."""
-    if workload != "jet128" or storage != "fp32" or not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILES.get(workload)
+    if storage != "fp32" or path is None or not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if "=" in line and not line.lstrip().startswith("#"):
                 k, v = line.split("=", 1)
@@ -223,7 +225,9 @@ def main():
     single = None
     if a.single and a.workload != "tgv256":
         r = run_lattice("tgv256", "fp32", max(1, a.steps // 2), max(1, a.warmup // 2), a.kernel)
+        t1 = measured_traffic("tgv256", "fp32") if a.kernel == "fused" else None
         single = {"workload": describe("tgv256", r["p"])["workload"], "nodes": r["nodes"], "value": r["glups"],
+                  "traffic": t1, "traffic_vs_algorithmic": t1 / (r["bpn"] * r["nodes"]) if t1 else None,
                   "unit": "GLUPS", "kernel_ms": r["kernel_ms"], "bytes_per_node": r["bpn"],
                   "roofline_frac": r["achieved"] / HBM_PEAK_GBS if r["achieved"] else None,
                   "frac_of_copy_ceiling": r["achieved"] / copy["gbps"] if (copy and r["achieved"]) else None,
