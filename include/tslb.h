@@ -183,6 +183,24 @@ int tslb_set_kernel(tslb_ctx *ctx, int kernel, int chunk_z);
  * ceiling and as the reference for scaling hardware byte counters. */
 int tslb_copy_bandwidth(int device, size_t bytes, int iters, double *gbps, double *ms);
 
+/* ---- Time averages (jet statistics) ---------------------------------------
+ *
+ * The statistics the paper's jet analysis rests on (Results: mean phase field
+ * and mean axial velocity along the centreline and across the jet): once
+ * started, tslb_step adds, after every step whose index is a multiple of
+ * `every`, the phase field phi, the physical velocity u (half-force shifted)
+ * and u_z^2 of every node to binary64 sums on the device.  tslb_stats_start
+ * (every >= 1) clears the sums; tslb_stats_stop ends accumulation and keeps
+ * them.  Not accumulated while the context is in a serving group. */
+int tslb_stats_start(tslb_ctx *ctx, int32_t every);
+int tslb_stats_stop(tslb_ctx *ctx);
+
+/* Means over the samples taken so far: mean_phi (N), mean_u (3N), rms_uz (N,
+ * the root-mean-square fluctuation of u_z); each pointer may be NULL.
+ * *samples (may be NULL) receives the sample count.  Synchronises.
+ * TSLB_E_STATE if a field is requested before any sample was taken. */
+int tslb_stats_get(tslb_ctx *ctx, float *mean_phi, float *mean_u, float *rms_uz, int64_t *samples);
+
 /* Release the context and everything it allocated.  A member of a serving
  * group is first removed from it (after the group's queued work). */
 void tslb_destroy(tslb_ctx *ctx);

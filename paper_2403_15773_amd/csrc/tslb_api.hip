@@ -286,6 +286,11 @@ int tslb_step(tslb_ctx *c, int64_t nsteps) {
         }
         c->cur ^= 1;
         c->step += 1;
+        if (c->stats.every > 0 && c->step % c->stats.every == 0) {
+            HIP_TRY(c, launch_geometry(c, c->buf[c->cur].phi, c->scratch.geo, c->stream));
+            HIP_TRY(c, launch_stats_accum(c, c->buf[c->cur], c->scratch.geo, c->stats.sum, c->stream));
+            c->stats.samples += 1;
+        }
         if (c->p.check_interval > 0 && c->step % c->p.check_interval == 0) {
             double d[2];
             long long phi_sum;
@@ -466,6 +471,53 @@ int tslb_copy_bandwidth(int device, size_t bytes, int iters, double *gbps, doubl
     return rc;
 }
 
+int tslb_stats_start(tslb_ctx *c, int32_t every) {
+    if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    NOT_IN_GROUP(c);
+    if (every < 1) return fail(c, TSLB_E_INVAL, "every must be >= 1");
+    int rc = ensure_planes(c);
+    if (rc) return rc;
+    const size_t bytes = 5 * (size_t)c->geo.ld * sizeof(double);
+    if (!c->stats.sum) {
+        hipError_t e = hipMalloc((void **)&c->stats.sum, bytes);
+        if (e != hipSuccess) return fail(c, TSLB_E_NOMEM, std::string("hipMalloc(stats): ") + hipGetErrorString(e));
+    }
+    HIP_TRY(c, hipMemsetAsync(c->stats.sum, 0, bytes, c->stream));
+    c->stats.every = every;
+    c->stats.samples = 0;
+    return TSLB_OK;
+}
+
+int tslb_stats_stop(tslb_ctx *c) {
+    if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    NOT_IN_GROUP(c);
+    c->stats.every = 0;
+    return TSLB_OK;
+}
+
+int tslb_stats_get(tslb_ctx *c, float *mean_phi, float *mean_u, float *rms_uz, int64_t *samples) {
+    if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    NOT_IN_GROUP(c);
+    if (samples) *samples = c->stats.samples;
+    if (!mean_phi && !mean_u && !rms_uz) return TSLB_OK;
+    if (!c->stats.sum || c->stats.samples == 0) return fail(c, TSLB_E_STATE, "no samples: call tslb_stats_start and step");
+    const size_t N = (size_t)c->geo.N, ld = (size_t)c->geo.ld;
+    std::vector<double> h(5 * ld);
+    HIP_TRY(c, hipMemcpyAsync(h.data(), c->stats.sum, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const double inv = 1.0 / (double)c->stats.samples;
+    for (size_t i = 0; i < N; ++i) {
+        if (mean_phi) mean_phi[i] = (float)(h[i] * inv);
+        if (mean_u)
+            for (int a = 0; a < 3; ++a) mean_u[a * N + i] = (float)(h[(1 + a) * ld + i] * inv);
+        if (rms_uz) {
+            const double m = h[3 * ld + i] * inv, var = h[4 * ld + i] * inv - m * m;
+            rms_uz[i] = (float)std::sqrt(var > 0.0 ? var : 0.0);
+        }
+    }
+    return TSLB_OK;
+}
+
 void tslb_destroy(tslb_ctx *c) {
     if (!c) return;
     if (c->group) group_detach(c->group, c);
@@ -477,6 +529,7 @@ void tslb_destroy(tslb_ctx *c) {
     if (c->scratch.partial_i) (void)hipFree(c->scratch.partial_i);
     if (c->scratch.result) (void)hipFree(c->scratch.result);
     if (c->scratch.result_i) (void)hipFree(c->scratch.result_i);
+    if (c->stats.sum) (void)hipFree(c->stats.sum);
     if (c->owns_base && c->base) (void)hipFree(c->base);
     if (c->owns_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;

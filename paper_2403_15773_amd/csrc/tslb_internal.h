@@ -40,6 +40,14 @@ struct Scratch {
     size_t partial_blocks = 0;
 };
 
+// Time averages of the physical fields (jet statistics), accumulated every
+// `every` steps of tslb_step: binary64 sums of phi, u_x, u_y, u_z and u_z^2.
+struct Stats {
+    double *sum = nullptr;  // 5 planes of ld doubles
+    int every = 0;          // 0: not accumulating
+    long long samples = 0;
+};
+
 struct StepTimer {
     bool enabled = false;
     std::vector<hipEvent_t> ev;  // pairs (start, stop) per timed launch
@@ -68,6 +76,7 @@ struct tslb_ctx {
     bool owns_stream = false;
     tslb::Scratch scratch;
     tslb::StepTimer timer;
+    tslb::Stats stats;
     int kernel = TSLB_KERNEL_FUSED;  // step kernel selected by tslb_set_kernel
     int chunk_z = 0;                 // z planes per workgroup of the fused kernel (0: automatic)
     int cu_count = 256;              // compute units of the device
@@ -108,5 +117,7 @@ hipError_t launch_step_fused_multi(const FusedDomain *doms, int ndom, int total_
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
 hipError_t launch_diagnostics(const tslb_ctx *c, StateView st, const Scratch &sc, hipStream_t s);
 size_t diagnostics_blocks(const tslb_ctx *c);
+// Add phi, u (= ubar + F/(2 rho), F from geo) and u_z^2 of every node of st to the sums.
+hipError_t launch_stats_accum(const tslb_ctx *c, StateView st, const float *geo, double *sum, hipStream_t s);
 
 }  // namespace tslb

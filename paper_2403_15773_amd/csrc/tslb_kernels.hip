@@ -276,6 +276,27 @@ __global__ __launch_bounds__(kBlock) void k_diag_final(const double *partial, co
     }
 }
 
+// ---- time averages (jet statistics) ----
+
+// Sums over time of phi, the physical velocity u = ubar + F/(2 rho) and u_z^2 at
+// every node (binary64, one thread per node; boundary layers included).
+template <int ST>
+__global__ __launch_bounds__(kBlock) void k_stats_accum(Geo g, Scales sc, StateView st, const float *__restrict__ geo,
+                                                        double *__restrict__ sum) {
+    long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.N) return;
+    const long long ld = g.ld;
+    float m[10];
+    load_raw<ST>(st, g, sc, id, m);
+    const float h = 0.5f / (1.0f + m[0]);
+    const double u0 = m[1] + h * geo[6 * ld + id], u1 = m[2] + h * geo[7 * ld + id], u2 = m[3] + h * geo[8 * ld + id];
+    sum[id] += st.phi ? (double)phi_to_float(st.phi[id]) : 0.0;
+    sum[ld + id] += u0;
+    sum[2 * ld + id] += u1;
+    sum[3 * ld + id] += u2;
+    sum[4 * ld + id] += u2 * u2;
+}
+
 // ---- the gather step (simple reference kernel) ----
 
 // One thread per interior destination x: for each velocity c_i, read the raw
@@ -436,6 +457,12 @@ hipError_t launch_step_gather(const tslb_ctx *c, StateView in, const float *geo,
 size_t diagnostics_blocks(const tslb_ctx *c) {
     long long b = grid_for(c->geo.N);
     return (size_t)(b < 1024 ? b : 1024);
+}
+
+hipError_t launch_stats_accum(const tslb_ctx *c, StateView st, const float *geo, double *sum, hipStream_t s) {
+    TSLB_DISPATCH(c->storage, k_stats_accum, dim3(grid_for(c->geo.N)), dim3(kBlock), 0, s, c->geo, c->scales, st, geo,
+                  sum);
+    return hipGetLastError();
 }
 
 hipError_t launch_diagnostics(const tslb_ctx *c, StateView st, const Scratch &sc, hipStream_t s) {

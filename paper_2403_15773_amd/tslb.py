@@ -29,7 +29,7 @@ EXPORTS = [
     "tslb_diagnostics", "tslb_step_index", "tslb_set_timing", "tslb_last_step_kernel_ms", "tslb_set_kernel",
     "tslb_copy_bandwidth", "tslb_destroy", "tslb_last_error",
     "tslb_group_create", "tslb_group_admit", "tslb_group_poll", "tslb_group_status", "tslb_group_destroy",
-    "tslb_group_last_error",
+    "tslb_group_last_error", "tslb_stats_start", "tslb_stats_stop", "tslb_stats_get",
 ]
 KERNEL_FUSED, KERNEL_GATHER = 0, 1
 
@@ -105,6 +105,9 @@ def load_library(path: str = LIB_PATH):
                                                  ctypes.POINTER(ctypes.c_int64)]),
             "tslb_group_destroy": (None, [vp]),
             "tslb_group_last_error": (ctypes.c_char_p, [vp]),
+            "tslb_stats_start": (ctypes.c_int, [vp, ctypes.c_int32]),
+            "tslb_stats_stop": (ctypes.c_int, [vp]),
+            "tslb_stats_get": (ctypes.c_int, [vp, _F, _F, _F, ctypes.POINTER(ctypes.c_int64)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -251,6 +254,28 @@ class Simulation:
 
     def last_step_kernel_ms(self):
         return self.lib.tslb_last_step_kernel_ms(self.h)
+
+    def stats_start(self, every=1):
+        """Accumulate time averages of phi, u and u_z^2 every `every` steps."""
+        self._check(self.lib.tslb_stats_start(self.h, int(every)))
+
+    def stats_stop(self):
+        self._check(self.lib.tslb_stats_stop(self.h))
+
+    def stats_samples(self) -> int:
+        """Samples accumulated since the last stats_start (0 before any)."""
+        n = ctypes.c_int64()
+        self._check(self.lib.tslb_stats_get(self.h, None, None, None, ctypes.byref(n)))
+        return n.value
+
+    def stats(self):
+        """dict: mean_phi, mean_u (3, ...), rms_uz, samples; raises with no samples."""
+        sh = self.shape
+        mp, mu, rz = np.empty(sh, np.float32), np.empty((3,) + sh, np.float32), np.empty(sh, np.float32)
+        n = ctypes.c_int64()
+        self._check(self.lib.tslb_stats_get(self.h, mp.ctypes.data_as(_F), mu.ctypes.data_as(_F),
+                                            rz.ctypes.data_as(_F), ctypes.byref(n)))
+        return {"mean_phi": mp, "mean_u": mu, "rms_uz": rz, "samples": n.value}
 
     def set_kernel(self, kernel="fused", chunk_z=0):
         k = {"fused": KERNEL_FUSED, "gather": KERNEL_GATHER}[kernel] if isinstance(kernel, str) else int(kernel)
