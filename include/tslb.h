@@ -90,7 +90,7 @@ typedef struct tslb_params {
     double sigma;            /* surface tension >= 0 (Eq. 20) */
     double width;            /* interface width W > 0 */
     double gamma;            /* anti-diffusion constant of Eq. 24; <= 0 selects 2/W */
-    double eps;              /* n = G/(|G| + eps) (Eq. 21); < 0 selects the default 1e-4 */
+    double eps;              /* n = G/(|G| + eps) (Eq. 21); >= 1e-30, or < 0 for the default 1e-4 */
     double inlet_u;          /* nozzle velocity U (TSLB_BC_INLET) */
     double inlet_d;          /* nozzle diameter D; axis at ((nx-1)/2, (ny-1)/2) */
     double inlet_noise;      /* relative amplitude a of the inlet perturbation */

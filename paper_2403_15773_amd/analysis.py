@@ -1,11 +1,15 @@
 """Jet statistics from time-averaged fields (host-side post-processing).
 
 The averages come from the device (``Simulation.stats()``); this module only
-reads them: the centreline profile along the jet axis, the decay law of the
-centreline velocity U/U_c(z) = (z - z0) / (B D) over a chosen window (the
-inverse slope B is the decay constant the Results section compares with
-experiments), and the half-width b(z) where the mean axial velocity drops to
-half its centreline value.
+reads them (Results, self-similarity of the jets):
+* the centreline values along the jet axis;
+* the linear law of an inverse centreline value, ref / X_c(z) = (z - z0) / (B D)
+  beyond the potential core, for the axial velocity (ref = U) and for the phase
+  field (ref = 1); the paper reports a slope 1/B of about 1/6.5 per diameter;
+* the Gaussian exponent K of a radial profile X / X_c = exp(-K eta^2) with
+  eta = r / (z - z0) (the paper compares K = 80 for the phase field and K = 75
+  for the axial velocity with experiments);
+* the half-width b(z) where a profile falls to half its centreline value.
 """
 from __future__ import annotations
 
@@ -28,7 +32,8 @@ def centreline(field, axis_x=None, axis_y=None):
 
 def decay_constant(uc, U, D, z_window):
     """Fit U/U_c(z) = (z - z0)/(B D) on z in [z_window[0], z_window[1]) (plane
-    indices); returns (B, z0/D)."""
+    indices); returns (B, z0/D).  With U = 1 and the centreline phase field it
+    gives the slope of 1/phi_c."""
     z = np.arange(len(uc), dtype=np.float64)
     sel = (z >= z_window[0]) & (z < z_window[1])
     slope, icept = np.polyfit(z[sel] / D, U / np.asarray(uc, np.float64)[sel], 1)
@@ -61,3 +66,15 @@ def half_width(plane, axis_x=None, axis_y=None):
         return float("nan")
     k = below[0]
     return float(r[k - 1] + (0.5 * c - prof[k - 1]) * (r[k] - r[k - 1]) / (prof[k] - prof[k - 1]))
+
+
+def gaussian_exponent(plane, z, z0, cutoff=0.05, axis_x=None, axis_y=None):
+    """Least-squares K of ln(X/X_c) = -K eta^2, eta = r / (z - z0), over the
+    radial bins with X/X_c above `cutoff` (plane = the (ny, nx) slice at z;
+    z and z0 in lattice units)."""
+    r, prof = radial_profile(plane, axis_x=axis_x, axis_y=axis_y)
+    c = centreline(np.asarray(plane)[None], axis_x, axis_y)[0]
+    y = prof / c
+    sel = np.isfinite(y) & (y > cutoff) & (y < 1.0)
+    eta2 = (r[sel] / (z - z0)) ** 2
+    return float(-np.sum(eta2 * np.log(y[sel])) / np.sum(eta2 * eta2))

@@ -68,6 +68,12 @@ bool validate(const tslb_params *p, std::string &why) {
     if (!(1.0 / (3.0 * p->nu + 0.5) < 2.0)) { why = "omega must stay below 2"; return false; }
     if (!(p->sigma >= 0.0) || !std::isfinite(p->sigma)) { why = "sigma must be >= 0"; return false; }
     if (!(p->width > 0.0) || !std::isfinite(p->width)) { why = "width must be positive"; return false; }
+    // eps regularises n = G/(|G| + eps) where G vanishes (Eq. 21): zero, non-finite
+    // or below the binary32 normal range would turn flat regions into NaN
+    if (!std::isfinite(p->eps) || (p->eps >= 0.0 && !(p->eps >= 1e-30))) {
+        why = "eps must be >= 1e-30 (or < 0 for the default)";
+        return false;
+    }
     if (p->storage < TSLB_STORE_FP32 || p->storage > TSLB_STORE_FP16Q) { why = "unknown storage"; return false; }
     if (p->components != 1 && p->components != 2) { why = "components must be 1 or 2"; return false; }
     if (p->check_interval < 0) { why = "check_interval must be >= 0"; return false; }

@@ -82,8 +82,8 @@ __device__ __forceinline__ float tr3_m0(float am, float a0, float ap) {
     return fmaf((am - a0) + (ap - a0), 1.0f / 6.0f, a0);
 }
 
-// 1/x for x near 1 (a density): the hardware reciprocal refined by one
-// Newton-Raphson step, e = 1 - x r, r' = r + r e, within an ulp of 1/x.
+// 1/x for a normal x (a density near 1, or |G| + eps): the hardware reciprocal
+// refined by one Newton-Raphson step, e = 1 - x r, r' = r + r e, within an ulp.
 __device__ __forceinline__ float recip(float x) {
     const float r = __builtin_amdgcn_rcpf(x);
     return fmaf(r, fmaf(-x, r, 1.0f), r);
@@ -238,7 +238,16 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
     float mom[10];
     int32_t phi_next[2] = {0, 0};
 
-    auto plane_of = [&](int z) { return wrap_or_clamp(z, g.nz, g.per[2]); };
+    // z is uniform and at most a few planes outside [0, nz): wrap by whole periods
+    // (no integer division in the loop)
+    auto plane_of = [&](int z) {
+        if (g.per[2]) {
+            while (z < 0) z += g.nz;
+            while (z >= g.nz) z -= g.nz;
+            return z;
+        }
+        return z < 0 ? 0 : (z >= g.nz ? g.nz - 1 : z);
+    };
     auto load_moments = [&](int z, float m[10]) {
         const long long id = col_src + plane * plane_of(z);
 #pragma unroll
@@ -471,7 +480,8 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
                             if (cy) G1 = fmaf(w * cy, d, G1);
                             if (cz) G2 = fmaf(w * cz, d, G2);
                         }
-                const float inv = 1.0f / (sqrtf(G0 * G0 + G1 * G1 + G2 * G2) + eps);
+                // hardware square root (1 ulp) and a refined reciprocal: |G| + eps >= eps
+                const float inv = recip(__builtin_amdgcn_sqrtf(fmaf(G0, G0, fmaf(G1, G1, G2 * G2))) + eps);
                 float *n = &sm.n[it % 3][0][0];
                 n[gi] = G0 * inv;
                 n[NGEO + gi] = G1 * inv;

@@ -64,7 +64,7 @@ def test_defaults_and_required_bytes(lib):
 
 @pytest.mark.parametrize("field,value", [
     ("nu", 0.0), ("nu", -1.0), ("width", 0.0), ("sigma", -1e-3), ("storage", 7), ("abi_version", 99), ("components", 3), ("components", 0),
-    ("nx", 0), ("check_interval", -1)])
+    ("nx", 0), ("check_interval", -1), ("eps", 0.0), ("eps", 1e-40), ("eps", float("nan"))])
 def test_invalid_parameters_rejected_on_host(lib, field, value):
     p = tslb.Params()
     lib.tslb_params_init(ctypes.byref(p))

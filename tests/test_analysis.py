@@ -38,3 +38,16 @@ def test_half_width_of_a_gaussian_profile():
 def test_radial_profile_of_a_constant_is_constant():
     r, prof = analysis.radial_profile(np.full((32, 32), 3.0))
     assert np.allclose(prof, 3.0) and r[0] == 0.5
+
+
+def test_gaussian_exponent_of_a_self_similar_profile():
+    """b = spread (z - z0 D) with exp(-ln2 r^2 / b^2) is exp(-K eta^2) with
+    K = ln2 / spread^2 and eta = r / (z - z0 D)."""
+    f, _, _ = _synthetic_jet(nx=129, ny=129, nz=200, spread=0.1)
+    K = np.log(2.0) / 0.1 ** 2
+    for z in (80, 150):
+        assert analysis.gaussian_exponent(f[z], z, -16.0) == pytest.approx(K, rel=0.02)
+    # the slope of 1/phi_c: phi_c = B D / (z - z0 D) with U = 1
+    _, uc, _ = _synthetic_jet(U=1.0, B=6.5, z0=0.6)  # origin off the grid: 4.8
+    B, z0 = analysis.decay_constant(uc, 1.0, 8.0, (30, 200))
+    assert B == pytest.approx(6.5, rel=1e-9) and z0 == pytest.approx(0.6, abs=1e-9)
