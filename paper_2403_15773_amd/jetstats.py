@@ -70,8 +70,8 @@ def run(nx, ny, nz, d, u, re, we, steps, avg_from, every, seed=2, chunk=2000, z_
     mphi, uz = st["mean_phi"], st["mean_u"][2]
     phic, uc = analysis.centreline(mphi), analysis.centreline(uz)
     # beyond the potential core (about 6-7 D at high We) and clear of the last
-    # 5 D, where the outflow layer bends the mean flow
-    zw = z_window or (int(9 * d), int(nz - 5 * d))
+    # 8 D, where the outflow layer bends the mean flow of a 20 D box
+    zw = z_window or (int(8 * d), int(nz - 8 * d))
     if zw[1] - zw[0] < 2:  # a short box: the middle of it
         zw = (int(0.45 * nz), int(0.75 * nz))
     B_u, z0_u = analysis.decay_constant(uc, u, d, zw)

@@ -51,3 +51,9 @@ def test_gaussian_exponent_of_a_self_similar_profile():
     _, uc, _ = _synthetic_jet(U=1.0, B=6.5, z0=0.6)  # origin off the grid: 4.8
     B, z0 = analysis.decay_constant(uc, 1.0, 8.0, (30, 200))
     assert B == pytest.approx(6.5, rel=1e-9) and z0 == pytest.approx(0.6, abs=1e-9)
+
+
+def test_jetstats_rejects_an_empty_averaging_window():
+    from paper_2403_15773_amd import jetstats
+    with pytest.raises(SystemExit):
+        jetstats.main(["--steps", "100", "--avg-from", "100"])
