@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-oracle sample budget (0 = skip)")
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the copy-kernel ceiling probe (0 = skip)")
     ap.add_argument("--kernel", default="fused", choices=["fused", "gather"])
+    ap.add_argument("--probe", type=int, default=1, help="time the projection on ALU and matrix cores (0 = skip)")
     return ap.parse_args()
 
 
@@ -200,6 +201,25 @@ def cpu_baseline(p, st, budget_s):
                       % (steps, p["nx"], p["ny"], p["nz"], t2 - t0)}
 
 
+def projection_probe(nodes, reps):
+    """The moment-to-population projection timed on the vector ALU (the step's
+    tensor product) and as FP32 matrix-core tiles, on the same seeded inputs."""
+    import numpy as np
+
+    from paper_2403_15773_amd.tslb import PROJECTION_MFMA, PROJECTION_VALU
+    from paper_2403_15773_amd.tslb import projection_probe as probe
+    coef = np.random.default_rng(3).uniform(-0.05, 0.05, (16, nodes)).astype(np.float32)
+    flops = 2.0 * 27 * 16 * nodes * reps  # the map as a dense 27 x 16 product
+    res = {"nodes": nodes, "reps": reps, "flop_per_projection": 2 * 27 * 16}
+    for name, kind in (("valu", PROJECTION_VALU), ("mfma_fp32", PROJECTION_MFMA)):
+        ms, _ = probe(kind, coef, reps, iters=10, want_out=False)
+        res[name] = {"ms": ms, "tflops_equivalent": flops / (ms * 1e-3) / 1e12}
+    res["mfma_over_valu_time"] = res["mfma_fp32"]["ms"] / res["valu"]["ms"]
+    log("projection probe: valu %.4f ms, mfma fp32 %.4f ms (%.2fx the time)" % (
+        res["valu"]["ms"], res["mfma_fp32"]["ms"], res["mfma_over_valu_time"]))
+    return res
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -255,6 +275,7 @@ def main():
                      "frac_of_copy_ceiling": achieved / copy["gbps"] if (copy and achieved) else None},
         "storage_variants": variants,
         "single_component": single,
+        "projection_probe": projection_probe(1 << 22, 64) if a.probe else None,
         "serving": serving(a.serve) if a.serve > 0 else None,
         "cpu_baseline": cpu_baseline(p, m["st"], a.cpu_seconds),
     }

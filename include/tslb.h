@@ -183,6 +183,22 @@ int tslb_set_kernel(tslb_ctx *ctx, int kernel, int chunk_z);
  * ceiling and as the reference for scaling hardware byte counters. */
 int tslb_copy_bandwidth(int device, size_t bytes, int iters, double *gbps, double *ms);
 
+/* Measurement utility: the moment-to-population projection of the step (the 27
+ * brackets f_i/w_i - 1 - rho' of a node from its 16 scaled Hermite coefficients,
+ * Eqs. 15-19) evaluated `reps` times per node over `nodes` nodes, each time with
+ * every coefficient raised by 1e-3, and accumulated.  kind 0 = the tensor product
+ * on the vector ALU that the step uses; kind 1 = the same 27 x 16 map as FP32
+ * matrix-core tiles (v_mfma_f32_32x32x2_f32).  coef_host: 16 x nodes floats
+ * (coefficient-major, order K1x K1y K1z K2xx K2yy K2zz K2xy K2xz K2yz K3xxy K3xxz
+ * K3yyx K3yyz K3zzx K3zzy K3xyz), host memory, read only.  nodes: a multiple of 64,
+ * at most 2^28.  out_host: NULL, or 27 x nodes floats (velocity-major, index
+ * 9 (c_z + 1) + (c_x + 1) + 3 (c_y + 1)) receiving the accumulated brackets.  *ms:
+ * mean kernel time over `iters` launches after one warm-up.  Allocates and frees
+ * its own device buffers on `device`.  TSLB_E_INVAL for bad arguments,
+ * TSLB_E_DEVICE for a HIP failure (message in tslb_last_error(NULL)). */
+int tslb_probe_projection(int32_t kind, const float *coef_host, int64_t nodes, int32_t reps, int32_t iters,
+                          int32_t device, float *out_host, double *ms);
+
 /* ---- Time averages (jet statistics) ---------------------------------------
  *
  * The statistics the paper's jet analysis rests on (Results: mean phase field

@@ -29,7 +29,7 @@ EXPORTS = [
     "tslb_diagnostics", "tslb_step_index", "tslb_set_timing", "tslb_last_step_kernel_ms", "tslb_set_kernel",
     "tslb_copy_bandwidth", "tslb_destroy", "tslb_last_error",
     "tslb_group_create", "tslb_group_admit", "tslb_group_poll", "tslb_group_status", "tslb_group_destroy",
-    "tslb_group_last_error", "tslb_stats_start", "tslb_stats_stop", "tslb_stats_get",
+    "tslb_group_last_error", "tslb_stats_start", "tslb_stats_stop", "tslb_stats_get", "tslb_probe_projection",
 ]
 KERNEL_FUSED, KERNEL_GATHER = 0, 1
 
@@ -96,6 +96,8 @@ def load_library(path: str = LIB_PATH):
             "tslb_set_kernel": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
             "tslb_copy_bandwidth": (ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, ctypes.c_int,
                                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+            "tslb_probe_projection": (ctypes.c_int, [ctypes.c_int32, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                                     ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double)]),
             "tslb_destroy": (None, [vp]),
             "tslb_last_error": (ctypes.c_char_p, [vp]),
             "tslb_group_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, vp, ctypes.POINTER(vp)]),
@@ -148,6 +150,24 @@ def copy_bandwidth(nbytes: int, iters: int = 20, device: int = 0):
     if rc != OK:
         raise TslbError(rc, lib.tslb_last_error(None).decode())
     return g.value, m.value
+
+
+PROJECTION_VALU, PROJECTION_MFMA = 0, 1
+
+
+def projection_probe(kind, coef, reps: int, iters: int = 10, device: int = 0, want_out: bool = True):
+    """(mean ms per launch, accumulated brackets (27, nodes) or None) of the
+    library's moment-to-population projection probe; coef is (16, nodes)."""
+    lib = load_library()
+    coef = np.ascontiguousarray(coef, np.float32)
+    nodes = coef.shape[1]
+    out = np.empty((27, nodes), np.float32) if want_out else None
+    m = ctypes.c_double()
+    rc = lib.tslb_probe_projection(int(kind), coef.ctypes.data, int(nodes), int(reps), int(iters), int(device),
+                                   None if out is None else out.ctypes.data, ctypes.byref(m))
+    if rc != OK:
+        raise TslbError(rc, lib.tslb_last_error(None).decode())
+    return m.value, out
 
 
 def required_bytes(params: Params) -> int:

@@ -100,3 +100,12 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.tslb_step_index(None) == -1
     assert lib.tslb_state_bytes(None) == 0
     lib.tslb_destroy(None)
+
+
+@pytest.mark.parametrize("kind,nodes,reps", [(2, 64, 1), (0, 100, 1), (1, 0, 1), (0, 64, 0)])
+def test_projection_probe_rejects_bad_arguments_on_host(lib, kind, nodes, reps):
+    import numpy as np
+    coef = np.zeros((16, max(nodes, 1)), np.float32)
+    ms = ctypes.c_double()
+    rc = lib.tslb_probe_projection(kind, coef.ctypes.data, nodes, reps, 1, 0, None, ctypes.byref(ms))
+    assert rc == tslb.E_INVAL and len(lib.tslb_last_error(None)) > 0
