@@ -353,3 +353,97 @@ def test_single_component_jet_parity():
     _say("single component mini-jet 24x24x40, 200 steps")
     p = inputs.jet_params(24, 24, 40, d=8.0, u=0.05, re=400.0, we=40.0, seed=9)
     _hydro_parity(p, inputs.quiescent(24, 24, 40), 200, "single-component jet", step0=5)
+
+
+def _pattern_state(nx, ny, nz):
+    """A smooth synthetic state on the whole lattice (binary32, separable products of
+    sines): phi in [0.1, 0.9] with interfaces about 10 nodes wide, |u| <= 0.02,
+    rho - 1 ~ 1e-3, P ~ 1e-4; cheap to generate for 5e8 nodes."""
+    x, y, z = (np.arange(n, dtype=np.float32) for n in (nx, ny, nz))
+    s = lambda v, L, ph=0.0: np.sin(np.float32(2 * np.pi / L) * v + np.float32(ph)).astype(np.float32)  # noqa: E731
+    sh = (nz, ny, nx)
+    st = {"rho_dev": np.empty(sh, np.float32), "u": np.empty((3,) + sh, np.float32),
+          "P": np.empty((6,) + sh, np.float32), "phi": np.empty(sh, np.float32)}
+    zy = lambda a, b: (a[:, None] * b[None, :])[:, :, None]  # noqa: E731
+    np.multiply(zy(s(z, 41.0), s(y, 29.0)), 0.4 * s(x, 37.0)[None, None, :], out=st["phi"])
+    st["phi"] += np.float32(0.5)
+    np.multiply(zy(s(z, 17.0), np.ones(ny, np.float32)), 1e-3 * s(x, 53.0, 1.0)[None, None, :], out=st["rho_dev"])
+    for a, (Lx, Ly, Lz) in enumerate(((23.0, 31.0, 47.0), (27.0, 19.0, 43.0), (33.0, 25.0, 39.0))):
+        np.multiply(zy(s(z, Lz, a), s(y, Ly, 2 * a)), 0.02 * s(x, Lx, 0.5 + a)[None, None, :], out=st["u"][a])
+    for k in range(6):
+        np.multiply(zy(s(z, 29.0 + k, k), s(y, 23.0 + k)), 1e-4 * s(x, 31.0 + k, 0.3 * k)[None, None, :], out=st["P"][k])
+    return st
+
+
+def _sub_box(n, c, wall):
+    """Index range [lo, lo + 9) along an axis of n nodes around node c, and whether it
+    touches the lattice's own boundary (then the box takes wall faces on both sides;
+    the far one lies outside the centre's dependency cone)."""
+    if not wall:
+        return c - 4, False
+    lo = min(max(c - 4, 0), n - 9)
+    return lo, lo == 0 or lo + 9 == n
+
+
+def test_large_jet_step_matches_oracle_at_sampled_nodes():
+    """The 512 x 512 x 2048 jet (D = 40, We = 2000) at full size, in the launch configuration
+    the benchmark times: one GPU step from a smooth synthetic state covering every plane,
+    against one FP64 oracle step on a 9^3 sub-box around each of 80 sampled nodes (interior,
+    near the free-slip walls and the outflow, lattice corners).  A node's update depends on
+    the state within 3 nodes of it, so the sub-box reproduces it exactly; the sub-box faces
+    are periodic, or walls where it touches the lattice's own free-slip or outflow faces.
+    Nodes within 5 planes of the inlet are not sampled (the inlet rule needs the global
+    coordinates)."""
+    from oracle import Oracle
+    from paper_2403_15773_amd.tslb import Simulation
+    p = inputs.WORKLOADS["jet512"]["params"]
+    nx, ny, nz = p["nx"], p["ny"], p["nz"]
+    rng = np.random.default_rng(7)
+    pts = [(int(rng.integers(0, nx)), int(rng.integers(0, ny)), int(rng.integers(5, nz))) for _ in range(64)]
+    pts += [(0, 0, 1000), (nx - 1, ny - 1, nz - 1), (0, 255, nz - 8), (nx - 1, 0, 7), (3, ny - 4, 1234),
+            (255, 255, nz - 2), (100, ny - 1, 600), (nx - 1, 300, nz - 1), (256, 256, 5), (1, 1, 2000),
+            (nx - 2, 17, 333), (40, ny - 2, nz - 5), (511, 128, 1024), (128, 0, 1500), (300, 300, nz - 3), (2, 509, 9)]
+    _say("large jet 512x512x2048: building the synthetic state")
+    st = _pattern_state(nx, ny, nz)
+    boxes = []
+    for (x, y, z) in pts:
+        (xl, wx), (yl, wy), (zl, wz) = _sub_box(nx, x, True), _sub_box(ny, y, True), _sub_box(nz, z, True)
+        sl = (slice(zl, zl + 9), slice(yl, yl + 9), slice(xl, xl + 9))
+        sub = {"rho": 1.0 + st["rho_dev"][sl].astype(np.float64), "phi": st["phi"][sl].astype(np.float64),
+               "u": st["u"][(slice(None),) + sl].astype(np.float64), "P": st["P"][(slice(None),) + sl].astype(np.float64)}
+        bc = (1, 1) if wx else (0, 0)
+        bc += (1, 1) if wy else (0, 0)
+        bc += (3, 3) if wz else (0, 0)
+        boxes.append((sub, bc, (z - zl, y - yl, x - xl)))
+    _say("large jet: GPU step from the synthetic state")
+    with Simulation(**p, eps=EPS) as s:
+        s.set_state(**st, step=0)
+        del st
+        s.step(1)
+        g = s.physical()
+    got = {k: [] for k in ("rho-1", "phi", "u", "P")}
+    ref = {k: [] for k in got}
+    for (sub, bc, c), (x, y, z) in zip(boxes, pts):
+        o = Oracle(9, 9, 9, nu=p["nu"], sigma=p["sigma"], width=p["width"], eps=EPS, bc=bc)
+        o.set_physical(**sub, step=0)
+        o.step(1)
+        r = o.physical()
+        o.close()
+        ref["rho-1"].append(r["rho"][c] - 1.0)
+        ref["phi"].append(r["phi"][c])
+        ref["u"].append(r["u"][(slice(None),) + c])
+        ref["P"].append(r["P"][(slice(None),) + c])
+        got["rho-1"].append(float(g["rho_dev"][z, y, x]))
+        got["phi"].append(float(g["phi"][z, y, x]))
+        got["u"].append(g["u"][:, z, y, x].astype(np.float64))
+        got["P"].append(g["P"][:, z, y, x].astype(np.float64))
+    errs = {}
+    for k in got:
+        a, b = np.array(got[k]), np.array(ref[k])
+        if a.ndim == 1:
+            errs[k] = np.abs(a - b).max() / np.abs(b).max()
+        else:
+            for j in range(a.shape[1]):
+                errs["%s%d" % (k, j)] = np.abs(a[:, j] - b[:, j]).max() / np.abs(b[:, j]).max()
+    _say("large jet, %d sampled nodes: " % len(pts) + " ".join("%s=%.2e" % kv for kv in errs.items()))
+    assert max(errs.values()) <= TOL_FP32
