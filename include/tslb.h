@@ -84,7 +84,8 @@ typedef struct tslb_ctx tslb_ctx;
 
 typedef struct tslb_params {
     int32_t abi_version;     /* must equal TSLB_ABI_VERSION */
-    int32_t nx, ny, nz;      /* lattice size; each >= 4 on a non-periodic axis, >= 1 otherwise */
+    int32_t nx, ny, nz;      /* lattice size; each >= 4 on a non-periodic axis, >= 1 otherwise;
+                                nx*ny < 2^30 and nx*ny*nz < 2^33 */
     int32_t bc[6];           /* TSLB_BC_* for faces -x,+x,-y,+y,-z,+z */
     double nu;               /* kinematic viscosity > 0; omega = 1/(3 nu + 1/2) < 2 (Eqs. 3-4) */
     double sigma;            /* surface tension >= 0 (Eq. 20) */
@@ -206,8 +207,11 @@ int tslb_probe_projection(int32_t kind, const float *coef_host, int64_t nodes, i
  * started, tslb_step adds, after every step whose index is a multiple of
  * `every`, the phase field phi, the physical velocity u (half-force shifted)
  * and u_z^2 of every node to binary64 sums on the device.  tslb_stats_start
- * (every >= 1) clears the sums; tslb_stats_stop ends accumulation and keeps
- * them.  Not accumulated while the context is in a serving group. */
+ * (every >= 1) clears the sums (allocating 40 bytes per node on first use;
+ * TSLB_E_INVAL for every < 1, TSLB_E_NOMEM if the allocation fails);
+ * tslb_stats_stop ends accumulation and keeps them.  A sample costs about as
+ * much as one step (the interface force is recomputed for the velocity).  Not
+ * accumulated while the context is in a serving group. */
 int tslb_stats_start(tslb_ctx *ctx, int32_t every);
 int tslb_stats_stop(tslb_ctx *ctx);
 
