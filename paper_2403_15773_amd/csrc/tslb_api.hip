@@ -270,10 +270,15 @@ int tslb_step(tslb_ctx *c, int64_t nsteps) {
     size_t timed = 0;
     if (tm.enabled) {
         size_t want = (size_t)(nsteps < (int64_t)max_timed ? nsteps : (int64_t)max_timed);
+        try {
+            tm.ev.reserve(2 * want);
+        } catch (const std::bad_alloc &) {
+            return fail(c, TSLB_E_NOMEM, "host allocation failed (timing events)");
+        }
         while (tm.ev.size() < 2 * want) {
             hipEvent_t ev;
             HIP_TRY(c, hipEventCreate(&ev));
-            tm.ev.push_back(ev);
+            tm.ev.push_back(ev);  // capacity reserved: does not throw
         }
         tm.used = 0;
     }
@@ -355,10 +360,14 @@ int tslb_phase(tslb_ctx *c, float *phi) {
         std::fill(phi, phi + N, 0.0f);
         return TSLB_OK;
     }
-    std::vector<int32_t> fixed(N);
-    HIP_TRY(c, hipMemcpyAsync(fixed.data(), c->buf[c->cur].phi, N * 4, hipMemcpyDeviceToHost, c->stream));
+    // the fixed-point words land in the caller's array and are converted in place
+    HIP_TRY(c, hipMemcpyAsync(phi, c->buf[c->cur].phi, N * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    for (size_t i = 0; i < N; ++i) phi[i] = phi_to_float(fixed[i]);
+    for (size_t i = 0; i < N; ++i) {
+        int32_t v;
+        std::memcpy(&v, phi + i, 4);
+        phi[i] = phi_to_float(v);
+    }
     return TSLB_OK;
 }
 
@@ -445,6 +454,11 @@ int tslb_copy_bandwidth(int device, size_t bytes, int iters, double *gbps, doubl
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     std::vector<float> times;
+    try {
+        times.reserve((size_t)iters);
+    } catch (const std::bad_alloc &) {
+        return fail(nullptr, TSLB_E_NOMEM, "host allocation failed");
+    }
     int rc = TSLB_OK;
     e = hipMalloc(&a, bytes);
     if (e == hipSuccess) e = hipMalloc(&b, bytes);
@@ -508,17 +522,29 @@ int tslb_stats_get(tslb_ctx *c, float *mean_phi, float *mean_u, float *rms_uz, i
     if (!mean_phi && !mean_u && !rms_uz) return TSLB_OK;
     if (!c->stats.sum || c->stats.samples == 0) return fail(c, TSLB_E_STATE, "no samples: call tslb_stats_start and step");
     const size_t N = (size_t)c->geo.N, ld = (size_t)c->geo.ld;
-    std::vector<double> h(5 * ld);
-    HIP_TRY(c, hipMemcpyAsync(h.data(), c->stats.sum, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    // the five sum planes come over in blocks of nodes through a bounded host buffer
+    const size_t blk = std::min(N, (size_t)1 << 22);
+    std::vector<double> h;
+    try {
+        h.resize(5 * blk);
+    } catch (const std::bad_alloc &) {
+        return fail(c, TSLB_E_NOMEM, "host allocation failed (statistics block)");
+    }
     const double inv = 1.0 / (double)c->stats.samples;
-    for (size_t i = 0; i < N; ++i) {
-        if (mean_phi) mean_phi[i] = (float)(h[i] * inv);
-        if (mean_u)
-            for (int a = 0; a < 3; ++a) mean_u[a * N + i] = (float)(h[(1 + a) * ld + i] * inv);
-        if (rms_uz) {
-            const double m = h[3 * ld + i] * inv, var = h[4 * ld + i] * inv - m * m;
-            rms_uz[i] = (float)std::sqrt(var > 0.0 ? var : 0.0);
+    for (size_t b0 = 0; b0 < N; b0 += blk) {
+        const size_t nb = std::min(blk, N - b0);
+        HIP_TRY(c, hipMemcpy2DAsync(h.data(), blk * sizeof(double), c->stats.sum + b0, ld * sizeof(double),
+                                    nb * sizeof(double), 5, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (size_t k = 0; k < nb; ++k) {
+            const size_t i = b0 + k;
+            if (mean_phi) mean_phi[i] = (float)(h[k] * inv);
+            if (mean_u)
+                for (int a = 0; a < 3; ++a) mean_u[a * N + i] = (float)(h[(1 + a) * blk + k] * inv);
+            if (rms_uz) {
+                const double m = h[3 * blk + k] * inv, var = h[4 * blk + k] * inv - m * m;
+                rms_uz[i] = (float)std::sqrt(var > 0.0 ? var : 0.0);
+            }
         }
     }
     return TSLB_OK;

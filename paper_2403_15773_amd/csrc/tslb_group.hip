@@ -155,6 +155,11 @@ int tslb_group_admit(tslb_group *g, tslb_ctx *c, int64_t nsteps) {
     if ((int)g->members.size() >= g->max_domains) return gfail(g, TSLB_E_NOMEM, "all domain slots are taken");
     const size_t bytes = 2 * c->buffer_bytes;
     if (g->bytes_in_use + bytes > g->budget) return gfail(g, TSLB_E_NOMEM, "HBM budget exhausted");
+    try {
+        g->members.reserve(g->members.size() + 1);
+    } catch (const std::bad_alloc &) {
+        return gfail(g, TSLB_E_NOMEM, "host allocation failed");
+    }
     // the group stream starts after everything already queued on the ctx
     GHIP_TRY(g, hipEventRecord(g->admit_ev, c->stream));
     GHIP_TRY(g, hipStreamWaitEvent(g->stream, g->admit_ev, 0));
@@ -162,7 +167,7 @@ int tslb_group_admit(tslb_group *g, tslb_ctx *c, int64_t nsteps) {
     // current state's layers are filled once here (the fill is idempotent)
     if (nsteps > 0) GHIP_TRY(g, launch_boundary(c, c->buf[c->cur], c->step, g->stream));
     // a member with no steps is done once the work queued so far has finished
-    g->members.push_back({c, nsteps, nsteps > 0 ? -1 : g->launches - 1, bytes});
+    g->members.push_back({c, nsteps, nsteps > 0 ? -1 : g->launches - 1, bytes});  // reserved: no throw
     g->bytes_in_use += bytes;
     c->group = g;
     return TSLB_OK;

@@ -14,6 +14,7 @@
 // operands.  The A operand holds the matrix entries A[m = lane % 32][k + lane / 32]
 // (rows 27-31 zero); each block accumulates its 32 x 32 result in 16 registers.
 #include <algorithm>
+#include <new>
 #include <vector>
 
 #include "tslb_hermite.h"
@@ -144,6 +145,11 @@ int tslb_probe_projection(int32_t kind, const float *coef_host, int64_t nodes, i
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     std::vector<float> times;
+    try {
+        times.reserve((size_t)iters);
+    } catch (const std::bad_alloc &) {
+        return probe_fail(TSLB_E_NOMEM, "host allocation failed");
+    }
     e = hipMalloc((void **)&d_in, in_bytes);
     if (e == hipSuccess) e = hipMalloc((void **)&d_out, out_bytes);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
