@@ -637,16 +637,33 @@ __global__ __launch_bounds__(NT) void k_step_fused_multi(const FusedDomain *__re
 
 }  // namespace fused
 
-// z planes per workgroup: the fixed choice of tslb_set_kernel, else the longest
-// chunk (at most 64 planes) that still gives every compute unit a workgroup.
-// Each chunk re-reads 6 planes of halo, so long chunks waste less.
+// z planes per workgroup: the fixed choice of tslb_set_kernel, else the chunk
+// length that minimises a compute unit's share of the work.  A workgroup on a
+// chunk of lz planes runs lz + 6 pipeline iterations (the prologue refills the
+// three-plane rings), and the W = tiles * ceil(nz / lz) workgroups spread over
+// the compute units, ceil(W / CUs) per unit, so the cost is
+// ceil(W / CUs) * (lz + 6).  Long chunks recompute less halo; short ones keep
+// every unit busy.  Ties go to the shorter chunk.
 int fused_chunk(const tslb_ctx *c) {
     using namespace fused;
     if (c->chunk_z > 0) return c->chunk_z;
     const long long tiles = (long long)((c->geo.nx + TX - 1) / TX) * ((c->geo.ny + TY - 1) / TY);
-    const long long chunks = (c->cu_count + tiles - 1) / tiles;
-    const long long lz = (c->geo.nz + chunks - 1) / chunks;
-    return (int)std::max(4LL, std::min(64LL, lz));
+    const long long cus = std::max(1, c->cu_count);
+    const int nz = c->geo.nz;
+    int best_lz = std::min(nz, 4);
+    long long best_cost = -1;
+    for (int k = 1; k <= nz; ++k) {  // k chunks of ceil(nz / k) planes
+        const int lz = (nz + k - 1) / k;
+        if (lz < 4 && k > 1) break;
+        if (k > 1 && lz == (nz + k - 2) / (k - 1)) continue;  // same length as k - 1 chunks
+        const long long w = tiles * ((nz + lz - 1) / lz);
+        const long long cost = (w + cus - 1) / cus * (long long)(lz + 6);
+        if (best_cost < 0 || cost <= best_cost) {
+            best_cost = cost;
+            best_lz = lz;
+        }
+    }
+    return best_lz;
 }
 
 int fused_work_items(const tslb_ctx *c, int lz) {
