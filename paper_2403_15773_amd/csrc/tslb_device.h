@@ -104,6 +104,35 @@ __device__ __forceinline__ float load_moment(const void *mom, long long ld, int 
     }
 }
 
+// The same moment in two halves, so that a prefetch can be issued long before
+// its value is used: load_moment_bits returns the stored word (a 16-bit word
+// zero-extended), decode_moment turns it into what load_moment returns.
+template <int ST>
+__device__ __forceinline__ uint32_t load_moment_bits(const void *mom, long long ld, int p, long long id) {
+    if constexpr (ST == ST_FP32) {
+        return ((const uint32_t *)mom)[p * ld + id];
+    } else if constexpr (ST == ST_FP16Q) {
+        if (p < 4) return ((const uint32_t *)mom)[p * ld + id];
+        return ((const uint16_t *)((const float *)mom + 4 * ld))[(p - 4) * ld + id];
+    } else {
+        return ((const uint16_t *)mom)[p * ld + id];
+    }
+}
+
+template <int ST>
+__device__ __forceinline__ float decode_moment(uint32_t b, int p, const Scales &sc) {
+    if constexpr (ST == ST_FP32) {
+        return __uint_as_float(b);
+    } else if constexpr (ST == ST_FP16Q) {
+        if (p < 4) return __uint_as_float(b);
+        return (float)__builtin_bit_cast(_Float16, (uint16_t)b) * sc.s2;
+    } else if constexpr (ST == ST_FP16) {
+        return (float)__builtin_bit_cast(_Float16, (uint16_t)b) * ((p >= 1 && p < 4) ? sc.s1 : sc.s2);
+    } else {
+        return __uint_as_float(b << 16) * ((p >= 1 && p < 4) ? sc.s1 : sc.s2);
+    }
+}
+
 template <int ST>
 __device__ __forceinline__ void store_moment(void *mom, long long ld, int p, long long id, float v, const Scales &sc) {
     if constexpr (ST == ST_FP32) {

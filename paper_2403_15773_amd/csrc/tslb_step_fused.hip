@@ -235,7 +235,9 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
     float cA = 0.f, cB = 0.f, cC = 0.f, eA = 0.f, eB = 0.f, eC = 0.f;  // curvature partial sums (S3a)
 
     // prefetched raw moments of the next source plane (own column)
-    float mom[10];
+    // (stored words: a 16-bit moment is converted only when the next iteration
+    // takes it over, so its load is not waited for in the iteration that issues it)
+    uint32_t mom[10] = {};  // defined before the first prefetch (decoded but unused until then)
     int32_t phi_next[2] = {0, 0};
 
     // z is uniform and at most a few planes outside [0, nz): wrap by whole periods
@@ -248,10 +250,10 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
         }
         return z < 0 ? 0 : (z >= g.nz ? g.nz - 1 : z);
     };
-    auto load_moments = [&](int z, float m[10]) {
+    auto load_moments = [&](int z, uint32_t m[10]) {
         const long long id = col_src + plane * plane_of(z);
 #pragma unroll
-        for (int p = 0; p < 10; ++p) m[p] = load_moment<ST>(in.mom, g.ld, p, id, sc);
+        for (int p = 0; p < 10; ++p) m[p] = load_moment_bits<ST>(in.mom, g.ld, p, id);
     };
     auto load_phi = [&](int z, int32_t v[2]) {
         const long long zoff = plane * plane_of(z);
@@ -288,7 +290,7 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
         // moments of source plane r + 1 for the next iteration
         float mom_cur[10];
 #pragma unroll
-        for (int k = 0; k < 10; ++k) mom_cur[k] = mom[k];
+        for (int k = 0; k < 10; ++k) mom_cur[k] = decode_moment<ST>(mom[k], k, sc);
         if (is_src && it >= 3) load_moments(r + 1, mom);
 
         // ================= phase A =================
