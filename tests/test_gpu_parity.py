@@ -247,13 +247,16 @@ def test_partial_tiles_jet_parity():
     assert_parity(g, r, TOL_FP32, "partial-tile jet")
 
 
-def test_fused_result_does_not_depend_on_z_chunking():
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16", "fp16q"])
+def test_fused_result_does_not_depend_on_z_chunking(storage):
+    """Bitwise the same state whatever the z chunk, for every storage type (16-bit
+    moments are prefetched a plane ahead as stored words)."""
     from paper_2403_15773_amd.tslb import Simulation
-    _say("chunk invariance droplet 32^3")
+    _say("chunk invariance droplet 32^3 %s" % storage)
     st = _f32(inputs.droplet(32, 8.0, 3.0, noise_amp=1e-3, seed=1))
     outs = []
     for chunk in (1, 5, 32, 0):  # 0: the library's own choice
-        s = Simulation(**inputs.droplet_params(32), eps=EPS)
+        s = Simulation(**inputs.droplet_params(32), eps=EPS, storage=storage)
         s.set_kernel("fused", chunk)
         s.set_state(**st)
         s.step(30)

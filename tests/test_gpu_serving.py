@@ -146,8 +146,9 @@ def test_group_mixes_one_and_two_component_lattices_bitwise():
     run alone."""
     from paper_2403_15773_amd.tslb import Group, Simulation
     _say("group mix of one- and two-component lattices")
-    reqs = _mix_requests()[:4]
-    cases = [(reqs[0], 1, "fp32"), (reqs[1], 2, "fp32"), (reqs[2], 1, "fp16q"), (reqs[3], 2, "fp16")]
+    reqs = _mix_requests()[:7]
+    cases = [(reqs[0], 1, "fp32"), (reqs[1], 2, "fp32"), (reqs[2], 1, "fp16q"), (reqs[3], 2, "fp16"),
+             (reqs[4], 2, "bf16"), (reqs[5], 2, "fp16q"), (reqs[6], 1, "bf16")]
 
     def make(r, comps, storage):
         p, f = serve.request_setup(r)
