@@ -92,3 +92,43 @@ def test_stats_bookkeeping():
         assert s.stats_samples() == 2
         with pytest.raises(TslbError):
             s.stats_start(0)
+
+
+def test_single_component_time_averages_match_oracle():
+    """One component (no phase plane): the 24 x 24 x 40 single-phase jet, sampling every
+    5 steps over steps 21..120; mean u and rms u_z against the sigma = 0 oracle's fields,
+    mean phi identically zero."""
+    from oracle import Oracle
+    from paper_2403_15773_amd.tslb import Simulation
+    from test_gpu_parity import _f32, _oracle_inputs
+    _say("stats single component mini-jet 24x24x40")
+    p = inputs.jet_params(24, 24, 40, d=8.0, u=0.05, re=400.0, we=40.0, seed=9)
+    st = _f32(inputs.quiescent(24, 24, 40))
+    every, first, last = 5, 20, 120
+    with Simulation(**p, components=1) as s:
+        s.set_state(rho_dev=st["rho_dev"], u=st["u"], P=st["P"], phi=None, step=0)
+        s.step(first)
+        s.stats_start(every)
+        s.step(last - first)
+        g = s.stats()
+    o = Oracle(p["nx"], p["ny"], p["nz"], nu=p["nu"], sigma=0.0, width=p["width"], eps=EPS, bc=p["bc"],
+               inlet_u=p["inlet_u"], inlet_d=p["inlet_d"], inlet_noise=p["inlet_noise"], seed=p["seed"])
+    o.set_physical(**_oracle_inputs(st), step=0)
+    o.step(first)
+    su, suz2, n = 0.0, 0.0, 0
+    for _ in range(last - first):
+        o.step(1)
+        if o.step_count % every == 0:
+            r = o.physical()
+            su = su + r["u"]
+            suz2 = suz2 + r["u"][2] ** 2
+            n += 1
+    o.close()
+    assert g["samples"] == n == 20
+    mu = su / n
+    rms = np.sqrt(np.maximum(suz2 / n - mu[2] ** 2, 0.0))
+    errs = {"u" + "xyz"[a]: np.abs(g["mean_u"][a] - mu[a]).max() / np.abs(mu[a]).max() for a in range(3)}
+    errs["rms_uz/U"] = np.abs(g["rms_uz"] - rms).max() / p["inlet_u"]
+    _say("single-component stats vs oracle: " + " ".join("%s=%.2e" % kv for kv in errs.items()))
+    assert not g["mean_phi"].any()
+    assert max(errs.values()) <= TOL
