@@ -53,6 +53,24 @@ struct Scales {
 // the stress Q in binary16 (Q/U^2).
 enum { ST_FP32 = 0, ST_FP16 = 1, ST_BF16 = 2, ST_FP16Q = 3 };
 
+// Memory views.  A kernel that takes its state pointers from a table in memory
+// (the multi-lattice step) accesses them as global_t pointers (G = true): the
+// compiler cannot tell otherwise that they address global memory and would use
+// flat instructions, which also hold up every LDS wait.  Where the pointers are
+// kernel arguments the plain view (G = false) compiles better (the compiler
+// infers global itself and keeps the plane addresses out of scalar registers).
+template <class T>
+using global_t = __attribute__((address_space(1))) T;
+template <bool G, class T> struct MemView { using P = T *; };
+template <class T> struct MemView<true, T> { using P = global_t<T> *; };
+template <bool G, class T>
+__device__ __forceinline__ typename MemView<G, T>::P mem(T *p) {
+    if constexpr (G)
+        return (typename MemView<G, T>::P)p;
+    else
+        return p;
+}
+
 template <int ST> struct Store;
 
 template <> struct Store<ST_FP32> {
@@ -107,15 +125,15 @@ __device__ __forceinline__ float load_moment(const void *mom, long long ld, int 
 // The same moment in two halves, so that a prefetch can be issued long before
 // its value is used: load_moment_bits returns the stored word (a 16-bit word
 // zero-extended), decode_moment turns it into what load_moment returns.
-template <int ST>
+template <int ST, bool G = false>
 __device__ __forceinline__ uint32_t load_moment_bits(const void *mom, long long ld, int p, long long id) {
     if constexpr (ST == ST_FP32) {
-        return ((const uint32_t *)mom)[p * ld + id];
+        return mem<G>((const uint32_t *)mom)[p * ld + id];
     } else if constexpr (ST == ST_FP16Q) {
-        if (p < 4) return ((const uint32_t *)mom)[p * ld + id];
-        return ((const uint16_t *)((const float *)mom + 4 * ld))[(p - 4) * ld + id];
+        if (p < 4) return mem<G>((const uint32_t *)mom)[p * ld + id];
+        return mem<G>((const uint16_t *)((const float *)mom + 4 * ld))[(p - 4) * ld + id];
     } else {
-        return ((const uint16_t *)mom)[p * ld + id];
+        return mem<G>((const uint16_t *)mom)[p * ld + id];
     }
 }
 
@@ -133,18 +151,21 @@ __device__ __forceinline__ float decode_moment(uint32_t b, int p, const Scales &
     }
 }
 
-template <int ST>
+template <int ST, bool G = false>
 __device__ __forceinline__ void store_moment(void *mom, long long ld, int p, long long id, float v, const Scales &sc) {
     if constexpr (ST == ST_FP32) {
-        ((float *)mom)[p * ld + id] = v;
+        mem<G>((float *)mom)[p * ld + id] = v;
     } else if constexpr (ST == ST_FP16Q) {
         if (p < 4)
-            ((float *)mom)[p * ld + id] = v;
+            mem<G>((float *)mom)[p * ld + id] = v;
         else
-            Store<ST_FP16>::store((_Float16 *)((float *)mom + 4 * ld) + (p - 4) * ld, id, v, sc.inv_s2);
+            mem<G>((_Float16 *)((float *)mom + 4 * ld) + (p - 4) * ld)[id] = (_Float16)(v * sc.inv_s2);
+    } else if constexpr (ST == ST_FP16) {
+        mem<G>((_Float16 *)mom + p * ld)[id] = (_Float16)(v * ((p >= 1 && p < 4) ? sc.inv_s1 : sc.inv_s2));
     } else {
-        using S = Store<ST>;
-        S::store((typename S::T *)mom + p * ld, id, v, (p >= 1 && p < 4) ? sc.inv_s1 : sc.inv_s2);
+        const uint32_t b = __float_as_uint(v * ((p >= 1 && p < 4) ? sc.inv_s1 : sc.inv_s2));
+        const uint32_t r = ((b & 0x7fffffffu) > 0x7f800000u) ? (b | 0x00400000u) : (b + 0x7fffu + ((b >> 16) & 1u));
+        mem<G>((uint16_t *)mom + p * ld)[id] = (uint16_t)(r >> 16);
     }
 }
 

@@ -141,8 +141,9 @@ __device__ __forceinline__ int xcd_work_item(int b, int nb) {
     return (xcd < rem8 ? xcd * (q8 + 1) : rem8 * (q8 + 1) + (xcd - rem8) * q8) + slot;
 }
 
-// One work item (a tile and a z chunk) of one lattice.
-template <int ST, bool PH>
+// One work item (a tile and a z chunk) of one lattice.  G: access the state
+// through global-address-space pointers (for state pointers read from memory).
+template <int ST, bool PH, bool G>
 __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phys &ph, const Scales &sc,
                                            const StateView &in, const StateView &out, int lz, int tiles_x,
                                            int tiles_y, unsigned long long step_next, int w) {
@@ -253,13 +254,13 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
     auto load_moments = [&](int z, uint32_t m[10]) {
         const long long id = col_src + plane * plane_of(z);
 #pragma unroll
-        for (int p = 0; p < 10; ++p) m[p] = load_moment_bits<ST>(in.mom, g.ld, p, id);
+        for (int p = 0; p < 10; ++p) m[p] = load_moment_bits<ST, G>(in.mom, g.ld, p, id);
     };
     auto load_phi = [&](int z, int32_t v[2]) {
         const long long zoff = plane * plane_of(z);
 #pragma unroll
         for (int k = 0; k < 2; ++k)
-            if (phi_item[k] >= 0) v[k] = in.phi[col_phi[k] + zoff];
+            if (phi_item[k] >= 0) v[k] = mem<G>(in.phi)[col_phi[k] + zoff];
     };
 
     const int nit = (z1 - z0) + 6;
@@ -573,8 +574,8 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
                         apply_boundary_rule(ph, g, zd == 1 ? 4 : 5, gxs, gys, step_next, mb, pb);
                         const long long ib = (long long)gxs + (long long)g.nx * gys + plane * zb;
 #pragma unroll
-                        for (int k = 0; k < 10; ++k) store_moment<ST>(out.mom, g.ld, k, ib, mb[k], sc);
-                        if constexpr (PH) out.phi[ib] = pb;
+                        for (int k = 0; k < 10; ++k) store_moment<ST, G>(out.mom, g.ld, k, ib, mb[k], sc);
+                        if constexpr (PH) mem<G>(out.phi)[ib] = pb;
                     }
                     // the node itself: interior, or on an x/y wall (face rule of step t+1)
                     int32_t po = phin;
@@ -584,8 +585,8 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
                     }
                     const long long id = (long long)gxs + (long long)g.nx * gys + plane * zd;
 #pragma unroll
-                    for (int k = 0; k < 10; ++k) store_moment<ST>(out.mom, g.ld, k, id, m[k], sc);
-                    if constexpr (PH) out.phi[id] = po;
+                    for (int k = 0; k < 10; ++k) store_moment<ST, G>(out.mom, g.ld, k, id, m[k], sc);
+                    if constexpr (PH) mem<G>(out.phi)[id] = po;
                 }
                 // carry: plane r gets X(+1) = XC, X(0) = X0; plane r+1 gets X(+1) = Xp
 #pragma unroll
@@ -616,7 +617,8 @@ template <int ST, bool PH>
 __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, StateView in, StateView out, int lz,
                                                    int tiles_x, int tiles_y, unsigned long long step_next) {
     __shared__ Smem<PH> sm;
-    step_fused<ST, PH>(sm, g, ph, sc, in, out, lz, tiles_x, tiles_y, step_next, xcd_work_item(blockIdx.x, gridDim.x));
+    step_fused<ST, PH, false>(sm, g, ph, sc, in, out, lz, tiles_x, tiles_y, step_next,
+                              xcd_work_item(blockIdx.x, gridDim.x));
 }
 
 // Several lattices in one launch: the work items of domain k are
@@ -634,7 +636,8 @@ __global__ __launch_bounds__(NT) void k_step_fused_multi(const FusedDomain *__re
             hi = mid - 1;
     }
     const FusedDomain &d = doms[lo];
-    step_fused<ST, PH>(sm, d.g, d.ph, d.sc, d.in, d.out, d.lz, d.tiles_x, d.tiles_y, d.step_next, w - d.work_begin);
+    step_fused<ST, PH, true>(sm, d.g, d.ph, d.sc, d.in, d.out, d.lz, d.tiles_x, d.tiles_y, d.step_next,
+                             w - d.work_begin);
 }
 
 }  // namespace fused
