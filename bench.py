@@ -19,6 +19,7 @@ The state is resident in HBM before the timed region.  Prints one JSON line:
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -195,10 +196,24 @@ def cpu_baseline(p, st, budget_s):
     t2 = time.perf_counter()
     steps = n + 1
     nodes = p["nx"] * p["ny"] * p["nz"]
+    # the same oracle on one core, continuing from the state reached (OpenMP is its only parallelism)
+    gomp = ctypes.CDLL("libgomp.so.1")
+    gomp.omp_set_num_threads(1)
+    try:
+        t3 = time.perf_counter()
+        o.step(1)
+        t4 = time.perf_counter()
+        n1 = max(0, min(100, int(budget_s / 3 / max(t4 - t3, 1e-6)) - 1))
+        o.step(n1)
+        t5 = time.perf_counter()
+    finally:
+        gomp.omp_set_num_threads(threads)
     o.close()
+    one = {"value": nodes * (n1 + 1) / (t5 - t3) / 1e9, "unit": "GLUPS", "cores": 1,
+           "sample": "%d step%s of the same workload on one thread, %.1f s" % (n1 + 1, "" if n1 == 0 else "s", t5 - t3)}
     return {"value": nodes * steps / (t2 - t0) / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
             "sample": "%d steps of the full %dx%dx%d workload (FP64 populations, OpenMP), %.1f s"
-                      % (steps, p["nx"], p["ny"], p["nz"], t2 - t0)}
+                      % (steps, p["nx"], p["ny"], p["nz"], t2 - t0), "single_core": one}
 
 
 def projection_probe(nodes, reps):

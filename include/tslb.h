@@ -30,6 +30,8 @@
  *     component order xx, yy, zz, xy, xz, yz.
  *   - Device memory is owned by the context unless the caller passes
  *     device_buffer, which must then stay allocated until tslb_destroy().
+ *   - A call that issues device work first makes the context's (or group's)
+ *     device current on the calling thread and leaves it current.
  */
 #ifndef TSLB_H
 #define TSLB_H

@@ -118,6 +118,10 @@ void set_thread_error(const std::string &msg) { g_thread_error = msg; }
         if ((c)->group) return fail((c), TSLB_E_STATE, "ctx is a member of a serving group");           \
     } while (0)
 
+// Every call that issues device work first makes the context's device current,
+// so a caller may switch devices between calls.
+#define ON_DEVICE(c) HIP_TRY((c), hipSetDevice((c)->p.device))
+
 extern "C" {
 
 void tslb_params_init(tslb_params *p) {
@@ -241,6 +245,7 @@ int tslb_set_state(tslb_ctx *c, const float *rho_dev, const float *u, const floa
                    int64_t step) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
     NOT_IN_GROUP(c);
+    ON_DEVICE(c);
     if (!rho_dev || !u || !pi_neq || (!phi && c->phase)) return fail(c, TSLB_E_INVAL, "every field is required");
     if (step < 0) return fail(c, TSLB_E_INVAL, "step must be >= 0");
     int rc = ensure_planes(c);
@@ -261,6 +266,7 @@ int tslb_set_state(tslb_ctx *c, const float *rho_dev, const float *u, const floa
 int tslb_step(tslb_ctx *c, int64_t nsteps) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
     NOT_IN_GROUP(c);
+    ON_DEVICE(c);
     if (nsteps < 0) return fail(c, TSLB_E_INVAL, "nsteps must be >= 0");
     if (!c->state_set) return fail(c, TSLB_E_STATE, "no state: call tslb_set_state first");
     int rc = c->kernel == TSLB_KERNEL_GATHER ? ensure_planes(c) : TSLB_OK;
@@ -324,6 +330,7 @@ int tslb_step(tslb_ctx *c, int64_t nsteps) {
 int tslb_sync(tslb_ctx *c) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
     NOT_IN_GROUP(c);
+    ON_DEVICE(c);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return TSLB_OK;
 }
@@ -331,6 +338,7 @@ int tslb_sync(tslb_ctx *c) {
 int tslb_moments(tslb_ctx *c, float *rho_dev, float *u, float *pi_neq) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
     NOT_IN_GROUP(c);
+    ON_DEVICE(c);
     if (!c->state_set) return fail(c, TSLB_E_STATE, "no state");
     int rc = ensure_planes(c);
     if (rc) return rc;
@@ -351,6 +359,7 @@ int tslb_moments(tslb_ctx *c, float *rho_dev, float *u, float *pi_neq) {
 int tslb_phase(tslb_ctx *c, float *phi) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
     NOT_IN_GROUP(c);
+    ON_DEVICE(c);
     if (!phi) return fail(c, TSLB_E_INVAL, "phi is NULL");
     if (!c->state_set) return fail(c, TSLB_E_STATE, "no state");
     int rc = fill_boundary_now(c);
@@ -376,6 +385,7 @@ size_t tslb_state_bytes(const tslb_ctx *c) { return c ? c->buffer_bytes : 0; }
 int tslb_get_state_raw(tslb_ctx *c, void *host, size_t bytes) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
     NOT_IN_GROUP(c);
+    ON_DEVICE(c);
     if (!host || bytes != c->buffer_bytes) return fail(c, TSLB_E_INVAL, "bytes must equal tslb_state_bytes()");
     if (!c->state_set) return fail(c, TSLB_E_STATE, "no state");
     int rc = fill_boundary_now(c);
@@ -388,6 +398,7 @@ int tslb_get_state_raw(tslb_ctx *c, void *host, size_t bytes) {
 int tslb_set_state_raw(tslb_ctx *c, const void *host, size_t bytes, int64_t step) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
     NOT_IN_GROUP(c);
+    ON_DEVICE(c);
     if (!host || bytes != c->buffer_bytes) return fail(c, TSLB_E_INVAL, "bytes must equal tslb_state_bytes()");
     if (step < 0) return fail(c, TSLB_E_INVAL, "step must be >= 0");
     HIP_TRY(c, hipMemcpyAsync(c->buf[c->cur].mom, host, bytes, hipMemcpyHostToDevice, c->stream));
@@ -400,6 +411,7 @@ int tslb_set_state_raw(tslb_ctx *c, const void *host, size_t bytes, int64_t step
 int tslb_diagnostics(tslb_ctx *c, double *mass, double *phase_sum, int64_t *step, int32_t *finite) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
     NOT_IN_GROUP(c);
+    ON_DEVICE(c);
     if (!c->state_set) return fail(c, TSLB_E_STATE, "no state");
     int rc = fill_boundary_now(c);
     if (rc) return rc;
@@ -435,7 +447,7 @@ int tslb_set_timing(tslb_ctx *c, int enable) {
 
 double tslb_last_step_kernel_ms(tslb_ctx *c) {
     if (!c || c->timer.used == 0) return 0.0;
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return 0.0;
+    if (hipSetDevice(c->p.device) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) return 0.0;
     double total = 0.0;
     for (size_t k = 0; k < c->timer.used; ++k) {
         float ms = 0.f;
@@ -494,6 +506,7 @@ int tslb_copy_bandwidth(int device, size_t bytes, int iters, double *gbps, doubl
 int tslb_stats_start(tslb_ctx *c, int32_t every) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
     NOT_IN_GROUP(c);
+    ON_DEVICE(c);
     if (every < 1) return fail(c, TSLB_E_INVAL, "every must be >= 1");
     int rc = ensure_planes(c);
     if (rc) return rc;
@@ -518,6 +531,7 @@ int tslb_stats_stop(tslb_ctx *c) {
 int tslb_stats_get(tslb_ctx *c, float *mean_phi, float *mean_u, float *rms_uz, int64_t *samples) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
     NOT_IN_GROUP(c);
+    ON_DEVICE(c);
     if (samples) *samples = c->stats.samples;
     if (!mean_phi && !mean_u && !rms_uz) return TSLB_OK;
     if (!c->stats.sum || c->stats.samples == 0) return fail(c, TSLB_E_STATE, "no samples: call tslb_stats_start and step");
@@ -552,6 +566,7 @@ int tslb_stats_get(tslb_ctx *c, float *mean_phi, float *mean_u, float *rms_uz, i
 
 void tslb_destroy(tslb_ctx *c) {
     if (!c) return;
+    (void)hipSetDevice(c->p.device);
     if (c->group) group_detach(c->group, c);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (hipEvent_t ev : c->timer.ev) (void)hipEventDestroy(ev);

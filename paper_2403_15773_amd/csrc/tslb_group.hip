@@ -153,6 +153,7 @@ int tslb_group_admit(tslb_group *g, tslb_ctx *c, int64_t nsteps) {
     if (c->kernel != TSLB_KERNEL_FUSED) return gfail(g, TSLB_E_STATE, "groups run the fused step kernel only");
     if (c->p.device != g->device) return gfail(g, TSLB_E_INVAL, "ctx and group are on different devices");
     if ((int)g->members.size() >= g->max_domains) return gfail(g, TSLB_E_NOMEM, "all domain slots are taken");
+    GHIP_TRY(g, hipSetDevice(g->device));
     const size_t bytes = 2 * c->buffer_bytes;
     if (g->bytes_in_use + bytes > g->budget) return gfail(g, TSLB_E_NOMEM, "HBM budget exhausted");
     try {
@@ -178,6 +179,7 @@ int tslb_group_poll(tslb_group *g, tslb_ctx **done, int32_t cap, int32_t *ndone)
     if (!ndone) return gfail(g, TSLB_E_INVAL, "ndone is NULL");
     if (cap < 0 || (cap > 0 && !done)) return gfail(g, TSLB_E_INVAL, "done/cap invalid");
     *ndone = 0;
+    GHIP_TRY(g, hipSetDevice(g->device));
     int rc = refresh_completed(g);
     if (rc) return rc;
     // retire members whose newest state is complete (admission order)
@@ -265,6 +267,7 @@ int tslb_group_status(const tslb_group *g, size_t *bytes_in_use, int32_t *member
 
 void tslb_group_destroy(tslb_group *g) {
     if (!g) return;
+    (void)hipSetDevice(g->device);
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     for (tslb_group::Member &m : g->members) m.ctx->group = nullptr;
     release_all(g);

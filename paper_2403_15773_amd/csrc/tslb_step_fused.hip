@@ -264,7 +264,7 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
     };
 
     const int nit = (z1 - z0) + 6;
-    // prologue: phase planes z0 - 3 and z0 - 2 staged (slots 0, 1); z0 - 1 prefetched
+    // prologue: phase planes z0 - 3 and z0 - 2 staged (slots 0, 1)
     if constexpr (PH) {
         int32_t v[2] = {0, 0};
         load_phi(z0 - 3, v);
@@ -275,7 +275,6 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
 #pragma unroll
         for (int k = 0; k < 2; ++k)
             if (phi_item[k] >= 0) sm.phi[1][phi_item[k]] = v[k];
-        load_phi(z0 - 1, phi_next);
     }
     __syncthreads();
 
@@ -293,6 +292,14 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
 #pragma unroll
         for (int k = 0; k < 10; ++k) mom_cur[k] = decode_moment<ST>(mom[k], k, sc);
         if (is_src && it >= 3) load_moments(r + 1, mom);
+        // phase plane p + 2, staged at the end of this iteration.  Issued here, next
+        // to the moment prefetch: at the loop latch the compiler waits for the
+        // moment words with a count that covers every memory operation issued so
+        // far (loads and stores share one counter), so a load issued late in the
+        // iteration would be waited for in full there.
+        if constexpr (PH) {
+            if (it + 3 <= nit) load_phi(p + 2, phi_next);
+        }
 
         // ================= phase A =================
         // ---- S3a: per-column partial sums of the curvature stencil (plane q) ----
@@ -605,7 +612,6 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
     #pragma unroll
                 for (int k = 0; k < 2; ++k)
                     if (phi_item[k] >= 0) sm.phi[(it + 2) & 3][phi_item[k]] = phi_next[k];
-                if (it + 4 <= nit) load_phi(p + 3, phi_next);
             }
         }
         __syncthreads();
