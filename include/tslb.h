@@ -174,8 +174,9 @@ double tslb_last_step_kernel_ms(tslb_ctx *ctx);
 
 /* Select the step kernel (TSLB_KERNEL_*) and, for the fused kernel, the number
  * of z planes a workgroup marches through: chunk_z >= 1 fixes it, 0 (the
- * default) lets the library choose per lattice (the longest chunk, at most 64,
- * that still gives every compute unit a workgroup).  Both kernels compute the
+ * default) lets the library choose per lattice (at most 128 planes, the length
+ * that minimises the rounds of workgroups per compute unit times the planes
+ * each round walks, its chunk plus a pipeline of 6).  Both kernels compute the
  * same step up to rounding, and the fused result does not depend on chunk_z. */
 int tslb_set_kernel(tslb_ctx *ctx, int kernel, int chunk_z);
 
