@@ -86,6 +86,37 @@ def test_invalid_boundary_sets_rejected(lib, bc):
     assert lib.tslb_required_bytes(ctypes.byref(p)) == 0
 
 
+def test_size_limits(lib):
+    """N = nx ny nz < 2^33 and nx ny < 2^30 (the inlet noise counter): the largest
+    lattices inside the limits are accepted with exact byte counts, the first
+    ones outside are rejected."""
+    p = tslb.Params()
+    lib.tslb_params_init(ctypes.byref(p))
+    p.nx, p.ny, p.nz = 1024, 1024, 8191  # N = 2^33 - 2^20, a multiple of 64
+    n = 1024 * 1024 * 8191
+    assert lib.tslb_required_bytes(ctypes.byref(p)) == 2 * 11 * 4 * n
+    p.nz = 8192  # N = 2^33
+    assert lib.tslb_required_bytes(ctypes.byref(p)) == 0
+    h = ctypes.c_void_p()
+    assert lib.tslb_create(ctypes.byref(p), ctypes.byref(h)) == tslb.E_INVAL and h.value is None
+    p.nx, p.ny, p.nz = 32768, 32767, 4  # nx ny = 2^30 - 2^15
+    assert lib.tslb_required_bytes(ctypes.byref(p)) == 2 * 11 * 4 * (32768 * 32767 * 4)
+    p.ny = 32768  # nx ny = 2^30
+    assert lib.tslb_required_bytes(ctypes.byref(p)) == 0
+
+
+def test_inlet_needs_a_positive_diameter(lib):
+    p = tslb.Params()
+    lib.tslb_params_init(ctypes.byref(p))
+    p.bc[:] = [tslb.BC_FREESLIP, tslb.BC_FREESLIP, tslb.BC_FREESLIP, tslb.BC_FREESLIP, tslb.BC_INLET, tslb.BC_OUTFLOW]
+    p.inlet_u = 0.05
+    for d in (0.0, -3.0, float("nan")):
+        p.inlet_d = d
+        assert lib.tslb_required_bytes(ctypes.byref(p)) == 0
+    p.inlet_d = 8.0
+    assert lib.tslb_required_bytes(ctypes.byref(p)) > 0
+
+
 def test_thin_axis_with_walls_rejected(lib):
     p = tslb.Params()
     lib.tslb_params_init(ctypes.byref(p))
