@@ -54,11 +54,13 @@ struct Scales {
 enum { ST_FP32 = 0, ST_FP16 = 1, ST_BF16 = 2, ST_FP16Q = 3 };
 
 // Memory views.  A kernel that takes its state pointers from a table in memory
-// (the multi-lattice step) accesses them as global_t pointers (G = true): the
-// compiler cannot tell otherwise that they address global memory and would use
-// flat instructions, which also hold up every LDS wait.  Where the pointers are
-// kernel arguments the plain view (G = false) compiles better (the compiler
-// infers global itself and keeps the plane addresses out of scalar registers).
+// (the multi-lattice step) can access them as global_t pointers (G = true): the
+// compiler cannot tell otherwise that they address global memory and uses flat
+// instructions, which also hold up every LDS wait.  The typed view keeps more
+// plane addresses in scalar registers, so it pays only where those do not spill
+// (binary32 storage of the multi-lattice step).  Where the pointers are kernel
+// arguments the plain view (G = false) compiles better (the compiler infers
+// global itself).
 template <class T>
 using global_t = __attribute__((address_space(1))) T;
 template <bool G, class T> struct MemView { using P = T *; };

@@ -143,7 +143,10 @@ __device__ __forceinline__ int xcd_work_item(int b, int nb) {
 
 // One work item (a tile and a z chunk) of one lattice.  G: access the state
 // through global-address-space pointers (for state pointers read from memory).
-template <int ST, bool PH, bool G>
+// MULTI marks the multi-lattice kernel's instantiation: it keeps that kernel's
+// copy of the step apart from the single-lattice kernel's, whose code is
+// otherwise changed (and slowed) by the second user of the same instantiation.
+template <int ST, bool PH, bool G, bool MULTI>
 __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phys &ph, const Scales &sc,
                                            const StateView &in, const StateView &out, int lz, int tiles_x,
                                            int tiles_y, unsigned long long step_next, int w) {
@@ -623,7 +626,7 @@ template <int ST, bool PH>
 __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, StateView in, StateView out, int lz,
                                                    int tiles_x, int tiles_y, unsigned long long step_next) {
     __shared__ Smem<PH> sm;
-    step_fused<ST, PH, false>(sm, g, ph, sc, in, out, lz, tiles_x, tiles_y, step_next,
+    step_fused<ST, PH, false, false>(sm, g, ph, sc, in, out, lz, tiles_x, tiles_y, step_next,
                               xcd_work_item(blockIdx.x, gridDim.x));
 }
 
@@ -642,8 +645,32 @@ __global__ __launch_bounds__(NT) void k_step_fused_multi(const FusedDomain *__re
             hi = mid - 1;
     }
     const FusedDomain &d = doms[lo];
-    step_fused<ST, PH, true>(sm, d.g, d.ph, d.sc, d.in, d.out, d.lz, d.tiles_x, d.tiles_y, d.step_next,
-                             w - d.work_begin);
+    // Every field is read once, here, into fresh local objects.  Used through the
+    // reference instead, the record's fields are loaded where the step needs them,
+    // inside the plane loop (the loads sit in conditional code, so the compiler
+    // does not hoist them), together with the 64-bit products derived from them;
+    // copied as a whole, the record stays in scratch memory.  Field by field, the
+    // step compiles to the same loop as the single-lattice kernel.  The state is
+    // accessed through global-address-space pointers for binary32 storage only:
+    // for 16-bit storage that view spills scalar registers, and the flat
+    // instructions cost less.
+    Geo g;
+    g.nx = d.g.nx; g.ny = d.g.ny; g.nz = d.g.nz;
+    g.per[0] = d.g.per[0]; g.per[1] = d.g.per[1]; g.per[2] = d.g.per[2];
+    g.N = d.g.N; g.ld = d.g.ld;
+    Phys ph;
+    ph.omega = d.ph.omega; ph.sigma = d.ph.sigma; ph.gamma = d.ph.gamma; ph.eps = d.ph.eps; ph.width = d.ph.width;
+    ph.inlet_u = d.ph.inlet_u; ph.inlet_d = d.ph.inlet_d; ph.inlet_noise = d.ph.inlet_noise;
+    ph.noise_key = d.ph.noise_key;
+    ph.bc[0] = d.ph.bc[0]; ph.bc[1] = d.ph.bc[1]; ph.bc[2] = d.ph.bc[2];
+    ph.bc[3] = d.ph.bc[3]; ph.bc[4] = d.ph.bc[4]; ph.bc[5] = d.ph.bc[5];
+    Scales sc;
+    sc.s2 = d.sc.s2; sc.s1 = d.sc.s1; sc.inv_s2 = d.sc.inv_s2; sc.inv_s1 = d.sc.inv_s1;
+    StateView in, out;
+    in.mom = d.in.mom; in.phi = d.in.phi; out.mom = d.out.mom; out.phi = d.out.phi;
+    const int lz = d.lz, tx = d.tiles_x, ty = d.tiles_y, wb = d.work_begin;
+    const unsigned long long sn = d.step_next;
+    step_fused<ST, PH, (ST == ST_FP32), true>(sm, g, ph, sc, in, out, lz, tx, ty, sn, w - wb);
 }
 
 }  // namespace fused
