@@ -4,9 +4,11 @@
 //   tau(c) = K1 . c + K2_aa h(c_a) + K2_ab c_a c_b + K3_aab h(c_a) c_b + K3_xyz c_x c_y c_z,
 // with h(c) = c^2 - 1/3, K1 = 3 J, K2_aa = 4.5 a2_aa, K2_ab = 9 a2_ab (a != b),
 // K3_aab = 13.5 a3_aab, K3_xyz = 27 a3_xyz.  The fused step (stage S4) evaluates
-// the same operations in the same order inline; the projection probe calls this
-// restatement, so it times the step's arithmetic.  (Routing the step itself
-// through this function changes its instruction schedule and costs ~3 %.)
+// the same tensor product inline, with the scale factors of the coefficients
+// folded into the constants of the multiply-adds that take them (eleven fewer
+// multiplies); the projection probe keeps the scaled coefficients as its inputs
+// and times this form of the same product.  (Routing the step itself through
+// this function changes its instruction schedule and costs ~3 %.)
 #pragma once
 
 #include <hip/hip_runtime.h>

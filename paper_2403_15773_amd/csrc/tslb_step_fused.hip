@@ -387,31 +387,51 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
                 const float a3zzx = fmaf(u2, fmaf(ru2, u0, 2.0f * mxz), u0 * mzz);
                 const float a3zzy = fmaf(u2, fmaf(ru2, u1, 2.0f * myz), u1 * mzz);
                 const float a3xyz = fmaf(ru0 * u1, u2, fmaf(u0, myz, fmaf(u1, mxz, u2 * mxy)));
-                const float K1x = 3.0f * Jx, K1y = 3.0f * Jy, K1z = 3.0f * Jz;
-                const float K2xx = 4.5f * a2xx, K2yy = 4.5f * a2yy, K2zz = 4.5f * a2zz;
-                const float K2xy = 9.0f * a2xy, K2xz = 9.0f * a2xz, K2yz = 9.0f * a2yz;
-                const float K3xxy = 13.5f * a3xxy, K3xxz = 13.5f * a3xxz, K3yyx = 13.5f * a3yyx;
-                const float K3yyz = 13.5f * a3yyz, K3zzx = 13.5f * a3zzx, K3zzy = 13.5f * a3zzy;
-                const float K3xyz = 27.0f * a3xyz;
+                // The scale factors of the coefficients (3 J, 4.5 a2_aa, 9 a2_ab, 13.5 a3_aab,
+                // 27 a3_xyz) are folded into the constants of the multiply-adds that take
+                // a coefficient as a slope or curvature term; only the five that enter as
+                // an addend are scaled explicitly.
+                const float K1y = 3.0f * Jy, K1z = 3.0f * Jz;
+                const float K2yy = 4.5f * a2yy, K2zz = 4.5f * a2zz, K2yz = 9.0f * a2yz;
                 // t = T0 + cz T1 + h(cz) T2; T0 = U0 + cy U1 + h(cy) U2 (per cx), etc.
                 float U0[3], U1[3], V0[3], W0[3];
-                quad3(0.0f, K1x, K2xx, U0[0], U0[1], U0[2]);  // tau = t - rho'
-                quad3(K1y, K2xy, K3xxy, U1[0], U1[1], U1[2]);
-                quad3(K1z, K2xz, K3xxz, V0[0], V0[1], V0[2]);
-                W0[0] = K2zz - K3zzx;
+                {   // U0 = quad3(0, 3 Jx, 4.5 a2xx): tau = t - rho'
+                    const float m = 3.0f * a2xx;
+                    U0[1] = -1.5f * a2xx;
+                    U0[0] = fmaf(-3.0f, Jx, m);
+                    U0[2] = fmaf(3.0f, Jx, m);
+                }
+                {   // U1 = quad3(3 Jy, 9 a2xy, 13.5 a3xxy)
+                    const float m = fmaf(9.0f, a3xxy, K1y);
+                    U1[1] = fmaf(-4.5f, a3xxy, K1y);
+                    U1[0] = fmaf(-9.0f, a2xy, m);
+                    U1[2] = fmaf(9.0f, a2xy, m);
+                }
+                {   // V0 = quad3(3 Jz, 9 a2xz, 13.5 a3xxz)
+                    const float m = fmaf(9.0f, a3xxz, K1z);
+                    V0[1] = fmaf(-4.5f, a3xxz, K1z);
+                    V0[0] = fmaf(-9.0f, a2xz, m);
+                    V0[2] = fmaf(9.0f, a2xz, m);
+                }
+                W0[0] = fmaf(-13.5f, a3zzx, K2zz);
                 W0[1] = K2zz;
-                W0[2] = K2zz + K3zzx;
+                W0[2] = fmaf(13.5f, a3zzx, K2zz);
 #pragma unroll
                 for (int ix = 0; ix < 3; ++ix) {
                     const float cx = (float)(ix - 1);
-                    const float U2 = fmaf(K3yyx, cx, K2yy);   // linear in cx
-                    const float V1 = fmaf(K3xyz, cx, K2yz);
+                    const float U2 = ix == 1 ? K2yy : fmaf(13.5f * cx, a3yyx, K2yy);  // linear in cx
+                    const float V1 = ix == 1 ? K2yz : fmaf(27.0f * cx, a3xyz, K2yz);
                     float T0[3], T1[3], T2[3];
                     quad3(U0[ix], U1[ix], U2, T0[0], T0[1], T0[2]);
-                    quad3(V0[ix], V1, K3yyz, T1[0], T1[1], T1[2]);
-                    T2[0] = W0[ix] - K3zzy;
+                    {   // T1 = quad3(V0, V1, 13.5 a3yyz)
+                        const float m = fmaf(9.0f, a3yyz, V0[ix]);
+                        T1[1] = fmaf(-4.5f, a3yyz, V0[ix]);
+                        T1[0] = m - V1;
+                        T1[2] = m + V1;
+                    }
+                    T2[0] = fmaf(-13.5f, a3zzy, W0[ix]);
                     T2[1] = W0[ix];
-                    T2[2] = W0[ix] + K3zzy;
+                    T2[2] = fmaf(13.5f, a3zzy, W0[ix]);
 #pragma unroll
                     for (int iy = 0; iy < 3; ++iy) {
                         const int k = ix + 3 * iy;
