@@ -35,7 +35,8 @@ BYTES_PER_NODE_1C = {"fp32": 80, "fp16": 40, "bf16": 40, "fp16q": 56}  # one com
 # HBM traffic of the fused step from rocprofv3 counters, valid while the kernel
 # sources hash to the value recorded next to the figures
 TRAFFIC_FILES = {"jet128": os.path.join(ROOT, "profiles", "fused_step_jet128_traffic.txt"),
-                 "tgv256": os.path.join(ROOT, "profiles", "fused_step_tgv256_1c_traffic.txt")}
+                 "tgv256": os.path.join(ROOT, "profiles", "fused_step_tgv256_1c_traffic.txt"),
+                 "jet512": os.path.join(ROOT, "profiles", "fused_step_jet512_traffic.txt")}
 KERNEL_SOURCES = ["paper_2403_15773_amd/csrc/tslb_step_fused.hip", "paper_2403_15773_amd/csrc/tslb_device.h"]
 
 
