@@ -239,7 +239,7 @@ def projection_probe(nodes, reps):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % a.gpus, file=sys.stderr)
+        print("bench.py: the TSLB step here runs on one GPU (multi-GPU sharding is a design only); --gpus %d is not supported" % a.gpus, file=sys.stderr)
         sys.exit(2)
     from paper_2403_15773_amd.tslb import copy_bandwidth
 

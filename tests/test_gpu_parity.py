@@ -116,7 +116,7 @@ def test_degenerate_periodic_lattices(shape):
     # On a lattice with a thin axis, the components of u and P along it vanish in
     # the continuum and are computed by cancellation between populations of the
     # size of rho'; binary32 resolves them only to ~1e-7 of the tensor's largest
-    # component.  So each component is judged against its tensor's largest one.
+    # component.  So each component is measured against its tensor's largest one.
     errs = {}
     groups = [("u", r["u"], g["u"]), ("P", r["P"], g["P"])]
     for name, ref, got in groups:
