@@ -247,6 +247,30 @@ def test_partial_tiles_jet_parity():
     assert_parity(g, r, TOL_FP32, "partial-tile jet")
 
 
+@pytest.mark.parametrize("name,bc", [
+    ("closed no-slip box", (4, 4, 4, 4, 4, 4)),
+    ("channel: free-slip x, no-slip y, periodic z", (1, 1, 4, 4, 0, 0)),
+    ("no-slip z walls, periodic x and y", (0, 0, 0, 0, 4, 4)),
+    ("no-slip and free-slip faces, outflow at +z", (4, 1, 1, 4, 4, 3)),
+])
+def test_walled_box_parity(name, bc):
+    """Boundary rules other than the jet's: a drop with a random velocity field in a
+    ragged box (partial tiles at every wall) whose faces take the no-slip,
+    free-slip and outflow rules in several combinations (Eqs. 9-10 with the
+    rule of each face), 60 steps against the oracle."""
+    _say("walled box %s bc=%s fp32 60 steps" % (name, bc))
+    nx, ny, nz = 36, 20, 24
+    x, y, z = inputs.grid_coords(nx, ny, nz)
+    st = inputs.quiescent(nx, ny, nz)
+    r2 = (x - 17.2) ** 2 + (y - 9.6) ** 2 + (z - 11.3) ** 2
+    st["phi"] = 0.5 * (1 - np.tanh(2 * (np.sqrt(r2) - 5.5) / 3.0))
+    node = np.arange(nx * ny * nz, dtype=np.uint64)
+    st["u"] = 0.01 * np.stack([inputs.noise(5, 0, 0, node, a).reshape(nz, ny, nx) for a in range(3)])
+    p = dict(nx=nx, ny=ny, nz=nz, nu=0.03, sigma=0.01, width=3.0, bc=bc)
+    g, r = run_both(p, st, 60)
+    assert_parity(g, r, TOL_FP32, "walled box (%s)" % name)
+
+
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16", "fp16q"])
 def test_fused_result_does_not_depend_on_z_chunking(storage):
     """Bitwise the same state whatever the z chunk, for every storage type (16-bit
