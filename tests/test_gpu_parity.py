@@ -363,6 +363,20 @@ def _hydro_parity(p, state, steps, label, step0=0):
     assert not bad, bad
 
 
+@pytest.mark.parametrize("bc", [(4, 4, 4, 4, 4, 4), (1, 1, 4, 4, 0, 0), (4, 1, 0, 0, 1, 3)])
+def test_single_component_walled_box_parity(bc):
+    """One component in a ragged box with no-slip, free-slip and outflow faces: a
+    random flow with density noise, 120 steps against the oracle at sigma = 0."""
+    _say("single component walled 36x20x24 bc=%s, 120 steps" % (bc,))
+    nx, ny, nz = 36, 20, 24
+    st = inputs.quiescent(nx, ny, nz)
+    node = np.arange(nx * ny * nz, dtype=np.uint64)
+    st["u"] = 0.02 * np.stack([inputs.noise(6, 0, 0, node, a).reshape(nz, ny, nx) for a in range(3)])
+    st["rho"] = 1.0 + 0.005 * inputs.noise(6, 3, 0, node, 0).reshape(nz, ny, nx)
+    _hydro_parity(dict(nx=nx, ny=ny, nz=nz, nu=0.02, sigma=0.0, width=3.0, bc=bc), st, 120,
+                  "single-component walled %s" % (bc,))
+
+
 def test_single_component_periodic_flow_parity():
     """One component (no phase planes): a random flow on a 40 x 24 x 20 periodic box, 150 steps."""
     _say("single component periodic 40x24x20, 150 steps")
