@@ -138,6 +138,19 @@ def test_mini_jet_parity():
     assert_parity(g, r, TOL_FP32, "mini-jet")
 
 
+@pytest.mark.parametrize("lateral,top", [((0, 0, 0, 0), 3), ((4, 4, 1, 1), 4)])
+def test_inlet_jet_with_other_faces_parity(lateral, top):
+    """The inlet disc with lateral faces other than the jet's free-slip walls
+    (periodic; no-slip in x and free-slip in y) and a ragged 26 x 22 x 36 box
+    (the disc axis between nodes), outflow or a no-slip lid at +z, 150 steps."""
+    bc = tuple(lateral) + (2, top)
+    _say("inlet jet bc=%s fp32 150 steps" % (bc,))
+    p = inputs.jet_params(26, 22, 36, d=8.0, u=0.05, re=400.0, we=40.0, seed=11)
+    p["bc"] = bc
+    g, r = run_both(p, inputs.quiescent(26, 22, 36), 150, step0=3)
+    assert_parity(g, r, TOL_FP32, "inlet jet %s" % (bc,))
+
+
 def test_rest_state_is_bitwise_steady():
     from paper_2403_15773_amd.tslb import Simulation
     _say("rest state 16^3")
