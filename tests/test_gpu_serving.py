@@ -173,3 +173,58 @@ def test_group_mixes_one_and_two_component_lattices_bitwise():
     for s, a, (r, comps, storage) in zip(sims, alone, cases):
         assert np.array_equal(s.get_state_raw(), a), "L=%d %d component(s) %s differs" % (r.L, comps, storage)
         s.close()
+
+
+def test_group_of_walled_boxes_is_bitwise_equal_to_alone_runs():
+    """Lattices whose faces take different rules (closed no-slip box, channel,
+    outflow lid, a jet) in one multi-lattice launch: each member reads its own
+    rule table, so each ends bitwise equal to its run alone."""
+    from paper_2403_15773_amd import inputs
+    from paper_2403_15773_amd.tslb import Group, Simulation
+    _say("group of walled boxes")
+    nx, ny, nz = 36, 20, 24
+    node = np.arange(nx * ny * nz, dtype=np.uint64)
+    x, y, z = inputs.grid_coords(nx, ny, nz)
+    st = inputs.quiescent(nx, ny, nz)
+    st["phi"] = 0.5 * (1 - np.tanh(2 * (np.sqrt((x - 17.2) ** 2 + (y - 9.6) ** 2 + (z - 11.3) ** 2) - 5.5) / 3.0))
+    st["u"] = 0.01 * np.stack([inputs.noise(7, 0, 0, node, a).reshape(nz, ny, nx) for a in range(3)])
+    fields = dict(rho_dev=np.zeros((nz, ny, nx), np.float32), u=st["u"].astype(np.float32),
+                  P=np.zeros((6, nz, ny, nx), np.float32), phi=st["phi"].astype(np.float32))
+    cases = [((4, 4, 4, 4, 4, 4), 40), ((1, 1, 4, 4, 0, 0), 33), ((4, 1, 1, 4, 4, 3), 27)]
+
+    def make(bc):
+        s = Simulation(nx=nx, ny=ny, nz=nz, nu=0.03, sigma=0.01, width=3.0, bc=bc, eps=1e-4)
+        s.set_state(**fields)
+        return s
+
+    jet_p = inputs.jet_params(24, 24, 40, d=8.0, u=0.05, re=400.0, we=40.0, seed=9)
+
+    def make_jet():
+        s = Simulation(**jet_p, eps=1e-4)
+        q = inputs.quiescent(24, 24, 40)
+        s.set_state(rho_dev=np.zeros((40, 24, 24), np.float32), u=q["u"].astype(np.float32),
+                    P=q["P"].astype(np.float32), phi=q["phi"].astype(np.float32))
+        return s
+
+    alone = []
+    for bc, n in cases:
+        with make(bc) as s:
+            s.step(n)
+            alone.append(s.get_state_raw())
+    with make_jet() as s:
+        s.step(31)
+        alone.append(s.get_state_raw())
+    sims = [make(bc) for bc, _ in cases] + [make_jet()]
+    steps = [n for _, n in cases] + [31]
+    with Group(hbm_budget_bytes=1 << 30, max_domains=8) as g:
+        for s, n in zip(sims, steps):
+            assert g.admit(s, n)
+        left, polls = len(sims), 0
+        while left:
+            left -= len(g.poll())
+            polls += 1
+            assert polls < 10000
+    for s, a, n in zip(sims, alone, steps):
+        assert s.step_index == n
+        assert np.array_equal(s.get_state_raw(), a), "bc %s differs" % (s.params.bc[:],)
+        s.close()
