@@ -194,33 +194,37 @@ def test_conservation_diagnostics():
     assert d1["phase"] == d0["phase"]  # integer phase streaming conserves the sum exactly
 
 
-def test_checkpoint_resume_is_bitwise():
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16", "fp16q"])
+def test_checkpoint_resume_is_bitwise(storage):
     from paper_2403_15773_amd.tslb import Simulation
-    _say("checkpoint/resume mini-jet")
+    _say("checkpoint/resume mini-jet %s" % storage)
     p = inputs.jet_params(16, 16, 24, d=6.0, u=0.05, re=300.0, we=50.0, seed=5)
     st = _f32(inputs.quiescent(16, 16, 24))
-    a = Simulation(**p, eps=EPS)
+    a = Simulation(**p, eps=EPS, storage=storage)
     a.set_state(**st)
     a.step(60)
     ck = a.get_state_raw()
     a.step(40)
     end_a = a.get_state_raw()
-    b = Simulation(**p, eps=EPS)
+    b = Simulation(**p, eps=EPS, storage=storage)
     b.set_state_raw(ck, step=60)
     b.step(40)
     assert np.array_equal(end_a, b.get_state_raw())
+    a.close()
+    b.close()
 
 
-def test_runs_are_deterministic():
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16", "fp16q"])
+def test_runs_are_deterministic(storage):
     from paper_2403_15773_amd.tslb import Simulation
-    _say("determinism droplet 24^3")
+    _say("determinism droplet 24^3 %s" % storage)
     st = _f32(inputs.droplet(24, 6.0, 3.0, noise_amp=1e-3, seed=4))
     outs = []
     for _ in range(2):
-        s = Simulation(nx=24, ny=24, nz=24, nu=0.01, sigma=0.01, eps=EPS)
-        s.set_state(**st)
-        s.step(50)
-        outs.append(s.get_state_raw())
+        with Simulation(nx=24, ny=24, nz=24, nu=0.01, sigma=0.01, eps=EPS, storage=storage) as s:
+            s.set_state(**st)
+            s.step(50)
+            outs.append(s.get_state_raw())
     assert np.array_equal(outs[0], outs[1])
 
 
