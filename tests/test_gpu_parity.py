@@ -443,25 +443,13 @@ def _sub_box(n, c, wall):
     return lo, lo == 0 or lo + 9 == n
 
 
-def test_large_jet_step_matches_oracle_at_sampled_nodes():
-    """The 512 x 512 x 2048 jet (D = 40, We = 2000) at full size, in the launch configuration
-    the benchmark times: one GPU step from a smooth synthetic state covering every plane,
-    against one FP64 oracle step on a 9^3 sub-box around each of 80 sampled nodes (interior,
-    near the free-slip walls and the outflow, lattice corners).  A node's update depends on
-    the state within 3 nodes of it, so the sub-box reproduces it exactly; the sub-box faces
-    are periodic, or walls where it touches the lattice's own free-slip or outflow faces.
-    Nodes within 5 planes of the inlet are not sampled (the inlet rule needs the global
-    coordinates)."""
+def _sampled_step_parity(p, pts, label):
+    """One GPU step of the lattice p from the smooth synthetic state against one
+    FP64 oracle step on a 9^3 sub-box around each sampled node (see the tests)."""
     from oracle import Oracle
     from paper_2403_15773_amd.tslb import Simulation
-    p = inputs.WORKLOADS["jet512"]["params"]
     nx, ny, nz = p["nx"], p["ny"], p["nz"]
-    rng = np.random.default_rng(7)
-    pts = [(int(rng.integers(0, nx)), int(rng.integers(0, ny)), int(rng.integers(5, nz))) for _ in range(64)]
-    pts += [(0, 0, 1000), (nx - 1, ny - 1, nz - 1), (0, 255, nz - 8), (nx - 1, 0, 7), (3, ny - 4, 1234),
-            (255, 255, nz - 2), (100, ny - 1, 600), (nx - 1, 300, nz - 1), (256, 256, 5), (1, 1, 2000),
-            (nx - 2, 17, 333), (40, ny - 2, nz - 5), (511, 128, 1024), (128, 0, 1500), (300, 300, nz - 3), (2, 509, 9)]
-    _say("large jet 512x512x2048: building the synthetic state")
+    _say("%s: building the synthetic state" % label)
     st = _pattern_state(nx, ny, nz)
     boxes = []
     for (x, y, z) in pts:
@@ -473,7 +461,7 @@ def test_large_jet_step_matches_oracle_at_sampled_nodes():
         bc += (1, 1) if wy else (0, 0)
         bc += (3, 3) if wz else (0, 0)
         boxes.append((sub, bc, (z - zl, y - yl, x - xl)))
-    _say("large jet: GPU step from the synthetic state")
+    _say("%s: GPU step from the synthetic state" % label)
     with Simulation(**p, eps=EPS) as s:
         s.set_state(**st, step=0)
         del st
@@ -503,5 +491,41 @@ def test_large_jet_step_matches_oracle_at_sampled_nodes():
         else:
             for j in range(a.shape[1]):
                 errs["%s%d" % (k, j)] = np.abs(a[:, j] - b[:, j]).max() / np.abs(b[:, j]).max()
-    _say("large jet, %d sampled nodes: " % len(pts) + " ".join("%s=%.2e" % kv for kv in errs.items()))
+    _say("%s, %d sampled nodes: " % (label, len(pts)) + " ".join("%s=%.2e" % kv for kv in errs.items()))
     assert max(errs.values()) <= TOL_FP32
+
+def test_large_jet_step_matches_oracle_at_sampled_nodes():
+    """The 512 x 512 x 2048 jet (D = 40, We = 2000) at full size, in the launch configuration
+    the benchmark times: one GPU step from a smooth synthetic state covering every plane,
+    against one FP64 oracle step on a 9^3 sub-box around each of 80 sampled nodes (interior,
+    near the free-slip walls and the outflow, lattice corners).  A node's update depends on
+    the state within 3 nodes of it, so the sub-box reproduces it exactly; the sub-box faces
+    are periodic, or walls where it touches the lattice's own free-slip or outflow faces.
+    Nodes within 5 planes of the inlet are not sampled (the inlet rule needs the global
+    coordinates)."""
+    p = inputs.WORKLOADS["jet512"]["params"]
+    nx, ny, nz = p["nx"], p["ny"], p["nz"]
+    rng = np.random.default_rng(7)
+    pts = [(int(rng.integers(0, nx)), int(rng.integers(0, ny)), int(rng.integers(5, nz))) for _ in range(64)]
+    pts += [(0, 0, 1000), (nx - 1, ny - 1, nz - 1), (0, 255, nz - 8), (nx - 1, 0, 7), (3, ny - 4, 1234),
+            (255, 255, nz - 2), (100, ny - 1, 600), (nx - 1, 300, nz - 1), (256, 256, 5), (1, 1, 2000),
+            (nx - 2, 17, 333), (40, ny - 2, nz - 5), (511, 128, 1024), (128, 0, 1500), (300, 300, nz - 3), (2, 509, 9)]
+    _sampled_step_parity(p, pts, "large jet 512x512x2048")
+
+
+def test_paper_geometry_jet_step_matches_oracle_at_sampled_nodes():
+    """The 400 x 400 x 800 jet of the paper's geometry (D = 40, We = 2000) at full size:
+    a launch with partial tiles (400 = 12.5 tiles of 32 columns: the last tile column
+    is pulled inward and overlaps its neighbour) and chunks of 115 planes with a short
+    last one (800 = 6 x 115 + 110).  Sampled nodes include the overlapped columns and
+    both sides of every chunk boundary."""
+    p = inputs.jet_params(400, 400, 800, d=40, u=0.05, re=5000, we=2000, seed=3)
+    nx, ny, nz = p["nx"], p["ny"], p["nz"]
+    rng = np.random.default_rng(11)
+    pts = [(int(rng.integers(0, nx)), int(rng.integers(0, ny)), int(rng.integers(5, nz))) for _ in range(40)]
+    for k, zb in enumerate(range(115, 800, 115)):  # chunk boundaries
+        for dz in (-3, -1, 0, 2):
+            pts.append((int(rng.integers(368, 400)), int(rng.integers(0, ny)), zb + dz))
+        pts.append((int(rng.integers(0, 368)), 399 - k, zb))
+    pts += [(399, 399, 799), (368, 0, 400), (383, 200, 690), (384, 399, 691), (0, 399, 799), (399, 5, 6)]
+    _sampled_step_parity(p, pts, "paper-geometry jet 400x400x800")
