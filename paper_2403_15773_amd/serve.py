@@ -18,6 +18,7 @@ from __future__ import annotations
 import collections
 import math
 import time
+import concurrent.futures
 from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
@@ -100,6 +101,10 @@ class Record:
         return self.done - self.req.arrival
 
 
+def _create(backend, req, prepared):
+    return backend.create(req, prepared.result())
+
+
 def serve(requests, backend, budget_bytes, max_domains=64, clock=time.perf_counter, sleep=time.sleep,
           prepare_workers=4, on_done=None):
     """Run the stream; return one Record per request (in request order).
@@ -107,49 +112,78 @@ def serve(requests, backend, budget_bytes, max_domains=64, clock=time.perf_count
     Arrived requests wait in a FIFO queue; the head is admitted when its state
     bytes fit the budget next to the running ones and a slot is free (a head
     that does not fit blocks the queue: no overtaking).  Host-side initial
-    fields are prepared by a thread pool as requests arrive."""
+    fields are prepared by a thread pool as requests arrive.  Creating a
+    request's lattice (device allocation, upload of its fields) and finishing
+    a retired one (diagnostics, release) run on one worker thread, so the loop
+    that keeps the device's launch queue filled never waits for them; lattices
+    are admitted in the order their creation started."""
     pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
     queue = collections.deque()
     recs = {r.id: Record(r) for r in requests}
-    active = {}      # handle key -> Record
+    active = {}          # handle key -> (Record, bytes)
+    creating = collections.deque()  # (request, bytes, future of the handle), FIFO
+    finishing = []       # (Record, future of the finish info)
     in_use = 0
     pool = ThreadPoolExecutor(max_workers=max(1, prepare_workers))
+    worker = ThreadPoolExecutor(max_workers=1)
     futures = {}
     t0 = clock()
+
+    def collect(block):
+        for item in list(finishing):
+            rec, fut = item
+            if block or fut.done():
+                info = fut.result()
+                rec.finite = bool(info.get("finite", True))
+                rec.extra = info
+                finishing.remove(item)
+                if on_done:
+                    on_done(rec)
+
     try:
-        while pending or queue or active:
+        while pending or queue or active or creating:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
                 r = pending.popleft()
                 queue.append(r)
                 futures[r.id] = pool.submit(backend.prepare, r)
-            while queue and len(active) < max_domains:
+            while queue and len(active) + len(creating) < max_domains:
                 r = queue[0]
                 need = backend.required_bytes(r)
                 if in_use + need > budget_bytes:
-                    break
-                h = backend.create(r, futures.pop(r.id).result())
-                if not backend.admit(h, r.steps):
-                    backend.discard(h)
+                    if not active and not creating:
+                        raise ValueError("request %d needs %d bytes, more than the budget of %d"
+                                         % (r.id, need, budget_bytes))
                     break
                 queue.popleft()
                 in_use += need
+                creating.append((r, need, worker.submit(_create, backend, r, futures.pop(r.id))))
+            while creating and creating[0][2].done():
+                r, need, fut = creating.popleft()
+                h = fut.result()
+                if not backend.admit(h, r.steps):  # the device refused: retry from the head of the queue
+                    backend.discard(h)
+                    in_use -= need
+                    queue.appendleft(r)
+                    futures[r.id] = pool.submit(backend.prepare, r)
+                    break
                 recs[r.id].admitted = clock() - t0
                 active[backend.key(h)] = (recs[r.id], need)
             if active:
                 for h in backend.poll():
                     rec, need = active.pop(backend.key(h))
                     rec.done = clock() - t0
-                    info = backend.finish(h)
-                    rec.finite = bool(info.get("finite", True))
-                    rec.extra = info
                     in_use -= need
-                    if on_done:
-                        on_done(rec)
+                    finishing.append((rec, worker.submit(backend.finish, h)))
+            elif creating:
+                concurrent.futures.wait([creating[0][2]], timeout=0.002)
             elif pending and not queue:
                 sleep(max(0.0, min(0.05, pending[0].arrival - (clock() - t0))))
+            collect(False)
+        collect(True)
     finally:
         pool.shutdown(wait=True)
+        worker.shutdown(wait=True)
     return [recs[r.id] for r in requests]
 
 

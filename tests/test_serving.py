@@ -152,6 +152,15 @@ def test_serving_loop_never_exceeds_the_slot_count():
     assert Counting.peak <= 2 and all(not math.isnan(r.done) for r in recs)
 
 
+def test_request_larger_than_the_budget_is_an_error():
+    """A request that could never fit (even on an empty device) fails instead of
+    blocking the queue for ever."""
+    reqs = serve.make_requests(3, rate=100.0, master_seed=2, sizes=(48,), steps=(5, 6))
+    clock = FakeClock()
+    with pytest.raises(ValueError, match="more than the budget"):
+        serve.serve(reqs, FakeDevice(clock), 88 * 32 ** 3, max_domains=4, clock=clock, sleep=clock.sleep)
+
+
 # ---- the group C-ABI: argument checks only (no device is touched) ----
 
 @pytest.fixture(scope="module")
