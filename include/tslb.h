@@ -237,8 +237,8 @@ const char *tslb_last_error(const tslb_ctx *ctx);
  * parameters, the mixed request stream of a solver service) together: every
  * tslb_group_poll() launches ONE fused step kernel that updates every member
  * with steps left (one launch per storage type and component count present),
- * so requests that
- * arrive while others run share the device from their first step on.  A
+ * so requests that arrive while others run share the device from their first
+ * step on.  A
  * member's update reads and writes only its own lattice (the step of the
  * method has no cross-node reduction), so its result is bitwise the one it
  * gets when run alone.  Admission is by HBM budget and slot count; members
