@@ -1,20 +1,26 @@
 """Throughput of the multicomponent TSLB step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload jet128] [--storage fp32]
-                    [--variants fp16,bf16] [--serve 256] [--cpu-seconds 15]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload jet512] [--storage fp32]
+                    [--variants fp16,bf16,fp16q] [--secondary jet128] [--serve 256] [--cpu-seconds 15]
 
 One step = the fused pull-stream-collide step over the whole lattice, which also
 writes the boundary layers of the state it produces (every row of the hot path).
 The state is resident in HBM before the timed region.  Prints one JSON line:
-  value / roofline  GLUPS (n_x n_y n_z n_steps / (1e9 T)) of the main run and the
-                    roofline of its dominant kernel (the fused step; algorithmic
-                    bytes = the state read once and written once: 88 B/node in
-                    binary32, 48 B/node with 16-bit moments), the kernel time
-                    measured with HIP events on the library's stream;
+  value / roofline  GLUPS (n_x n_y n_z n_steps / (1e9 T)) of the main run (by
+                    default the 512 x 512 x 2048 jet, the largest workload on one
+                    GPU) and the roofline of its dominant kernel (the fused step;
+                    algorithmic bytes = the state read once and written once:
+                    88 B/node in binary32, 48 B/node with 16-bit moments), the
+                    kernel time measured with HIP events on the library's stream
+                    around every launch of the timed region;
   storage_variants  the same workload with FP16/BF16-stored moments;
+  secondary         the 128 x 128 x 512 jet in binary32;
   serving           the seeded request stream run by continuous batching
                     (p50/p99 latency, aggregate GLUPS);
-  cpu_baseline      the FP64 CPU oracle timed on a bounded sample of the workload.
+  cpu_baseline      the FP64 CPU oracle timed on a bounded sample of the workload
+                    (of the 128 x 128 x 512 jet when the workload's FP64
+                    populations do not fit in host memory: 292 GB for the
+                    512 x 512 x 2048 jet).
 """
 from __future__ import annotations
 
@@ -45,9 +51,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="jet128", choices=["jet128", "jet512", "droplet32", "tgv256"])
+    ap.add_argument("--workload", default="jet512", choices=["jet128", "jet512", "droplet32", "tgv256"])
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16", "fp16q"])
     ap.add_argument("--variants", default="fp16,bf16,fp16q", help="other storage types timed on the same workload")
+    ap.add_argument("--secondary", default="jet128", help="another workload timed in binary32 ('' = skip)")
     ap.add_argument("--serve", type=int, default=256, help="requests in the serving stream (0 = skip)")
     ap.add_argument("--single", type=int, default=1, help="also time the one-component Taylor-Green vortex (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-oracle sample budget (0 = skip)")
@@ -125,8 +132,7 @@ def run_lattice(name, storage, steps, warmup, kernel="fused"):
     sim = Simulation(**p, eps=1e-4, storage=storage, u_scale=0.05, device=0)
     sim.set_kernel(kernel)
     if st is None:
-        # quiescent: rho = 1, u = 0, P = 0, phi = 0 is the all-zero raw state
-        sim.set_state_raw(np.zeros(sim.state_bytes, np.uint8), step=0)
+        sim.set_state_rest(step=0)  # quiescent: rho = 1, u = 0, P = 0, phi = 0
     else:
         one = p.get("components", 2) == 1
         sim.set_state(rho_dev=np.asarray(st["rho"] - 1.0, np.float32), u=np.asarray(st["u"], np.float32),
@@ -141,6 +147,7 @@ def run_lattice(name, storage, steps, warmup, kernel="fused"):
     sim.sync()
     t1 = time.perf_counter()
     kernel_ms = sim.last_step_kernel_ms()
+    times = sim.step_kernel_times()
     diag = sim.diagnostics()
     sim.close()
     T = t1 - t0
@@ -148,8 +155,10 @@ def run_lattice(name, storage, steps, warmup, kernel="fused"):
     achieved = bpn * nodes / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else None
     log("%s %s: %.3f s for %d steps, kernel %.4f ms/launch, finite=%s" % (name, storage, T, steps, kernel_ms,
                                                                           diag["finite"]))
+    spread = {"median": float(np.median(times)), "min": float(times.min()), "max": float(times.max()),
+              "launches": int(times.size)} if times.size else None
     return {"p": p, "st": st, "nodes": nodes, "T": T, "glups": nodes * steps / T / 1e9, "kernel_ms": kernel_ms,
-            "achieved": achieved, "bpn": bpn, "finite": diag["finite"]}
+            "kernel_ms_spread": spread, "achieved": achieved, "bpn": bpn, "finite": diag["finite"]}
 
 
 def serving(n_requests):
@@ -157,28 +166,42 @@ def serving(n_requests):
     droplet/jet, Re 500..5000, We 10..2000, 500..5000 steps) through the
     serving group."""
     from paper_2403_15773_amd import serve
-    from paper_2403_15773_amd.tslb import Group
+    from paper_2403_15773_amd.tslb import Group, device_memory
     reqs = serve.make_requests(n_requests, rate=20.0, master_seed=5)
-    budget = 64 << 30
-    log("serving %d requests" % n_requests)
+    free, total = device_memory(0)
+    budget = max(0, free - total // 16)  # admission by free HBM, less a reserve of 1/16 of the device
+    log("serving %d requests, budget %.1f GB of free HBM" % (n_requests, budget / 1e9))
     t0 = time.perf_counter()
     with Group(hbm_budget_bytes=budget, max_domains=64) as g:
-        recs = serve.serve(reqs, serve.GpuBackend(g), budget, max_domains=64)
-    s = serve.summarise(recs)
-    log("serving: p50 %.2f s, p99 %.2f s, %.2f GLUPS aggregate, %d unstable, %.1f s wall" % (
-        s["p50_latency_s"], s["p99_latency_s"], s["aggregate_glups"], s["unstable"], time.perf_counter() - t0))
+        backend = serve.GpuBackend(g)
+        recs = serve.serve(reqs, backend, budget, max_domains=64)
+        busy = backend.busy_seconds()
+    s = serve.summarise(recs, busy_s=busy)
+    log("serving: p50 %.2f s, p99 %.2f s, %.2f GLUPS aggregate (offered %.2f), device busy %.1f %%, %d unstable, "
+        "%.1f s wall" % (s["p50_latency_s"], s["p99_latency_s"], s["aggregate_glups"], s["offered_glups"],
+                         100 * s["device_busy_frac"], s["unstable"], time.perf_counter() - t0))
+    s["budget_bytes"] = budget
     s["stream"] = ("%d requests, Poisson arrivals 20/s (master seed 5), cubic L in {32,48,64,96,128}, droplet/jet "
-                   "50/50, Re log-U[500,5000], We log-U[10,2000], steps U{500..5000}, FP32, budget 64 GiB, "
-                   "64 domain slots" % n_requests)
+                   "50/50, Re log-U[500,5000], We log-U[10,2000], steps U{500..5000}, FP32, admitted by free HBM "
+                   "(hipMemGetInfo at the start, less 1/16 of the device), 64 domain slots" % n_requests)
     return s
 
 
-def cpu_baseline(p, st, budget_s):
+# Workloads whose FP64 population oracle does not fit in host memory take the
+# oracle's rate on a smaller lattice of the same set-up (the rate is per node).
+CPU_SAMPLE_WORKLOAD = {"jet512": "jet128"}
+
+
+def cpu_baseline(name, p, st, budget_s):
     """The FP64 oracle as it stands, on this host's cores, for a bounded number of
-    steps of the same workload; rate in GLUPS."""
+    steps of the same workload (or of CPU_SAMPLE_WORKLOAD's stand-in); rate in GLUPS."""
     if budget_s <= 0:
         return None
     import numpy as np
+
+    quoted = CPU_SAMPLE_WORKLOAD.get(name)
+    if quoted is not None:
+        p, st = workload_state(quoted)
 
     from oracle import Oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
@@ -212,9 +235,13 @@ def cpu_baseline(p, st, budget_s):
     o.close()
     one = {"value": nodes * (n1 + 1) / (t5 - t3) / 1e9, "unit": "GLUPS", "cores": 1,
            "sample": "%d step%s of the same workload on one thread, %.1f s" % (n1 + 1, "" if n1 == 0 else "s", t5 - t3)}
+    what = ("%d steps of the full %dx%dx%d workload (FP64 populations, OpenMP), %.1f s"
+            % (steps, p["nx"], p["ny"], p["nz"], t2 - t0))
+    if quoted is not None:
+        what = ("quoted from the %dx%dx%d jet of the same set-up (the %s lattice's FP64 populations do not fit in "
+                "host memory): %s" % (p["nx"], p["ny"], p["nz"], name, what))
     return {"value": nodes * steps / (t2 - t0) / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
-            "sample": "%d steps of the full %dx%dx%d workload (FP64 populations, OpenMP), %.1f s"
-                      % (steps, p["nx"], p["ny"], p["nz"], t2 - t0), "single_core": one}
+            "sample": what, "single_core": one}
 
 
 def projection_probe(nodes, reps):
@@ -258,6 +285,16 @@ def main():
                        "roofline_frac": r["achieved"] / HBM_PEAK_GBS if r["achieved"] else None,
                        "bytes_per_node": r["bpn"], "speedup_vs_%s" % a.storage: r["glups"] / m["glups"],
                        "finite": r["finite"]}
+    secondary = None
+    if a.secondary and a.secondary != a.workload:
+        r = run_lattice(a.secondary, "fp32", a.steps, a.warmup, a.kernel)
+        t2 = measured_traffic(a.secondary, "fp32") if a.kernel == "fused" else None
+        secondary = describe(a.secondary, r["p"]) | {
+            "storage": "fp32", "value": r["glups"], "unit": "GLUPS", "ms_per_step": r["T"] / a.steps * 1e3,
+            "kernel_ms": r["kernel_ms"], "kernel_ms_spread": r["kernel_ms_spread"], "bytes_per_node": r["bpn"],
+            "roofline_frac": r["achieved"] / HBM_PEAK_GBS if r["achieved"] else None,
+            "traffic": t2, "traffic_vs_algorithmic": t2 / (r["bpn"] * r["nodes"]) if t2 else None,
+            "finite": r["finite"]}
     single = None
     if a.single and a.workload != "tgv256":
         r = run_lattice("tgv256", "fp32", max(1, a.steps // 2), max(1, a.warmup // 2), a.kernel)
@@ -287,13 +324,15 @@ def main():
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, copy-kernel scaled)",
                      "traffic_vs_algorithmic": traffic / (m["bpn"] * nodes) if traffic else None,
                      "kernel": "%s step" % a.kernel, "bytes_per_node": m["bpn"], "kernel_ms": m["kernel_ms"],
+                     "kernel_ms_spread": m["kernel_ms_spread"],
                      "copy_ceiling": copy["gbps"] if copy else None,
                      "frac_of_copy_ceiling": achieved / copy["gbps"] if (copy and achieved) else None},
         "storage_variants": variants,
+        "secondary": secondary,
         "single_component": single,
         "projection_probe": projection_probe(1 << 22, 64) if a.probe else None,
         "serving": serving(a.serve) if a.serve > 0 else None,
-        "cpu_baseline": cpu_baseline(p, m["st"], a.cpu_seconds),
+        "cpu_baseline": cpu_baseline(a.workload, p, m["st"], a.cpu_seconds),
     }
     print(json.dumps(rec), flush=True)
 

@@ -43,14 +43,15 @@
 extern "C" {
 #endif
 
-#define TSLB_ABI_VERSION 2
+#define TSLB_ABI_VERSION 3
 
 enum {
     TSLB_OK = 0,
     TSLB_E_INVAL = -1,    /* bad argument or parameter set */
     TSLB_E_NOMEM = -2,    /* device or host allocation failed, or budget exceeded */
     TSLB_E_DEVICE = -3,   /* a HIP call failed */
-    TSLB_E_UNSTABLE = -4, /* a non-finite value appeared; state kept at the failing step */
+    TSLB_E_UNSTABLE = -4, /* a non-finite value appeared, or the mass left the bound of
+                             max_mass_drift; state kept at the failing step */
     TSLB_E_STATE = -5     /* call out of order (e.g. step before any state was set) */
 };
 
@@ -110,6 +111,11 @@ typedef struct tslb_params {
                                 regularised hydrodynamics alone (no phase plane in the state,
                                 F = 0; sigma, width, gamma and eps are ignored, tslb_phase returns
                                 zeros and the phase sum is 0) */
+    double max_mass_drift;   /* > 0: at every check (check_interval) the mass sum(rho) must stay
+                                within this relative distance of its value when stepping started
+                                from the last state set; else TSLB_E_UNSTABLE.  The method conserves
+                                mass on a closed lattice (periodic, no-slip or free-slip faces), to
+                                binary32 rounding; inlet and outflow faces exchange mass.  0 = off */
 } tslb_params;
 
 /* Fill *p with defaults: periodic 32^3, nu = 0.1, sigma = 0, W = 3, FP32, two components. */
@@ -135,8 +141,20 @@ int tslb_create(const tslb_params *p, tslb_ctx **out);
 int tslb_set_state(tslb_ctx *ctx, const float *rho_dev, const float *u, const float *pi_neq, const float *phi,
                    int64_t step);
 
-/* Queue nsteps fused steps (asynchronous unless check_interval triggers a
- * check, which synchronises and returns TSLB_E_UNSTABLE on a non-finite value). */
+/* Set the state of a fluid at rest at step `step`: rho = 1, u = 0, P = 0 and
+ * phi = 0 everywhere (in the stored deviation form every word is zero), the
+ * quiescent ambient into which the paper's jets are injected (Results, jet
+ * set-up).  No host transfer; the boundary layers are filled by the first
+ * tslb_step.  Synchronises. */
+int tslb_set_state_rest(tslb_ctx *ctx, int64_t step);
+
+/* Queue nsteps time steps of the method (Eqs. 5, 6, 8: every node's moments
+ * rebuilt from its neighbours' post-collision populations, with the phase
+ * field of Eqs. 22-24 and the boundary layers of Eqs. 9-10).  Asynchronous
+ * unless check_interval triggers a check, which synchronises and returns
+ * TSLB_E_UNSTABLE on a non-finite value or a mass outside max_mass_drift (the
+ * state is then the one of the failing step).  TSLB_E_STATE before any state
+ * was set. */
 int tslb_step(tslb_ctx *ctx, int64_t nsteps);
 
 /* Wait for queued work. */
@@ -148,6 +166,13 @@ int tslb_moments(tslb_ctx *ctx, float *rho_dev, float *u, float *pi_neq);
 
 /* Phase field phi (N) at the current step.  Synchronises. */
 int tslb_phase(tslb_ctx *ctx, float *phi);
+
+/* Device memory the context holds now, in bytes: its two state buffers, the
+ * diagnostics partials (a few kilobytes) and any scratch planes allocated at
+ * the time (those of running statistics, 76 B per node, or of the gather
+ * kernel, 36 B per node; set-state and readout release theirs before they
+ * return).  What a serving group charges against its budget.  0 for NULL. */
+size_t tslb_device_bytes(const tslb_ctx *ctx);
 
 /* Raw state as stored (bitwise checkpoint): bytes must equal tslb_state_bytes(). */
 size_t tslb_state_bytes(const tslb_ctx *ctx);
@@ -172,6 +197,12 @@ int tslb_set_timing(tslb_ctx *ctx, int enable);
  * no timed launch exists. */
 double tslb_last_step_kernel_ms(tslb_ctx *ctx);
 
+/* Per-launch durations (ms) of the fused step kernel over the last tslb_step()
+ * call made with timing enabled: up to cap values are written to ms (host
+ * array, may be NULL when cap is 0) and *count receives the number of timed
+ * launches (at most 8192 per call).  Synchronises. */
+int tslb_step_kernel_times(tslb_ctx *ctx, float *ms, int64_t cap, int64_t *count);
+
 /* Select the step kernel (TSLB_KERNEL_*) and, for the fused kernel, the number
  * of z planes a workgroup marches through: chunk_z >= 1 fixes it, 0 (the
  * default) lets the library choose per lattice (at most 128 planes, the length
@@ -179,6 +210,10 @@ double tslb_last_step_kernel_ms(tslb_ctx *ctx);
  * each round walks, its chunk plus a pipeline of 6).  Both kernels compute the
  * same step up to rounding, and the fused result does not depend on chunk_z. */
 int tslb_set_kernel(tslb_ctx *ctx, int kernel, int chunk_z);
+
+/* Free and total device memory of HIP device `device` in bytes (hipMemGetInfo):
+ * what a serving loop admits requests against. */
+int tslb_device_memory(int32_t device, size_t *free_bytes, size_t *total_bytes);
 
 /* Measurement utility: copy `bytes` (a multiple of 16) between two device
  * buffers it allocates on `device`, `iters` times with a plain streaming copy
@@ -251,7 +286,10 @@ const char *tslb_last_error(const tslb_ctx *ctx);
 typedef struct tslb_group tslb_group;
 
 /* Create a group on the current HIP device.  hbm_budget_bytes caps the summed
- * state bytes (two buffers per member) of the members; max_domains (1..4096)
+ * device bytes the members hold (two state buffers each, the diagnostics
+ * partials, and any scratch planes still allocated, e.g. those of running
+ * statistics); a caller admitting by free HBM derives it from
+ * tslb_device_memory().  max_domains (1..4096)
  * caps their count; stream is a hipStream_t for the group's launches, or NULL
  * for one the group creates.  Errors: TSLB_E_INVAL, TSLB_E_NOMEM,
  * TSLB_E_DEVICE (text from tslb_last_error(NULL)). */
@@ -274,6 +312,12 @@ int tslb_group_poll(tslb_group *g, tslb_ctx **done, int32_t cap, int32_t *ndone)
 /* Bytes charged to the budget, number of members and launches so far (each
  * pointer may be NULL). */
 int tslb_group_status(const tslb_group *g, size_t *bytes_in_use, int32_t *members, int64_t *launches);
+
+/* Device-busy time of the group: *busy_ms receives the summed durations of its
+ * completed launches (each from the start of its table upload to the end of
+ * its last kernel, HIP events on the group's stream) and *completed (may be
+ * NULL) their number.  Does not wait. */
+int tslb_group_busy(tslb_group *g, double *busy_ms, int64_t *completed);
 
 /* Wait for the group's work and release it; members become free contexts at
  * the step their last launched update reached. */

@@ -77,16 +77,52 @@ bool validate(const tslb_params *p, std::string &why) {
     if (p->storage < TSLB_STORE_FP32 || p->storage > TSLB_STORE_FP16Q) { why = "unknown storage"; return false; }
     if (p->components != 1 && p->components != 2) { why = "components must be 1 or 2"; return false; }
     if (p->check_interval < 0) { why = "check_interval must be >= 0"; return false; }
+    if (!(p->max_mass_drift >= 0.0) || !std::isfinite(p->max_mass_drift)) {
+        why = "max_mass_drift must be finite and >= 0";
+        return false;
+    }
     if (p->bc[4] == TSLB_BC_INLET && !(p->inlet_d > 0.0)) { why = "inlet_d must be positive"; return false; }
     return true;
 }
 
-// Scratch planes used by set-state, readout and the materialised-geometry step.
-int ensure_planes(tslb_ctx *c) {
-    if (c->scratch.stage && c->scratch.geo) return TSLB_OK;
-    size_t ld = (size_t)c->geo.ld;
-    if (!c->scratch.stage) HIP_TRY(c, hipMalloc((void **)&c->scratch.stage, 11 * ld * sizeof(float)));
-    if (!c->scratch.geo) HIP_TRY(c, hipMalloc((void **)&c->scratch.geo, 9 * ld * sizeof(float)));
+// Scratch planes (binary32, 80 B per node together) used by set-state and
+// readout (staging and geometry), by the statistics samples (geometry) and by
+// the materialised-geometry step (geometry).  Allocated on demand; an
+// allocation failure is TSLB_E_NOMEM.
+int ensure_planes(tslb_ctx *c, bool stage, bool geo) {
+    const size_t ld = (size_t)c->geo.ld;
+    if (stage && !c->scratch.stage) {
+        hipError_t e = hipMalloc((void **)&c->scratch.stage, 11 * ld * sizeof(float));
+        if (e != hipSuccess) {
+            c->scratch.stage = nullptr;
+            return fail(c, TSLB_E_NOMEM, std::string("hipMalloc(staging planes): ") + hipGetErrorString(e));
+        }
+    }
+    if (geo && !c->scratch.geo) {
+        hipError_t e = hipMalloc((void **)&c->scratch.geo, 9 * ld * sizeof(float));
+        if (e != hipSuccess) {
+            c->scratch.geo = nullptr;
+            return fail(c, TSLB_E_NOMEM, std::string("hipMalloc(geometry planes): ") + hipGetErrorString(e));
+        }
+    }
+    return TSLB_OK;
+}
+
+// Give back the scratch planes once a set-state or readout call is done with
+// them, so that between calls a context holds its two state buffers (what a
+// serving group charges) plus the few kilobytes of diagnostics partials.  The
+// geometry planes stay while statistics are sampled or the materialised-geometry
+// step is selected.  Synchronises the stream first.
+int release_planes(tslb_ctx *c) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->scratch.stage) {
+        HIP_TRY(c, hipFree(c->scratch.stage));
+        c->scratch.stage = nullptr;
+    }
+    if (c->scratch.geo && c->stats.every == 0 && c->kernel != TSLB_KERNEL_GATHER) {
+        HIP_TRY(c, hipFree(c->scratch.geo));
+        c->scratch.geo = nullptr;
+    }
     return TSLB_OK;
 }
 
@@ -109,6 +145,31 @@ int run_diagnostics(tslb_ctx *c, double out[2], long long *phi_fixed) {
 
 namespace tslb {
 void set_thread_error(const std::string &msg) { g_thread_error = msg; }
+
+bool validate_params(const tslb_params *p, std::string &why) { return validate(p, why); }
+
+void derive_layout(const tslb_params *p, Geo &g, Scales &sc) {
+    g.nx = p->nx; g.ny = p->ny; g.nz = p->nz;
+    for (int a = 0; a < 3; ++a) g.per[a] = p->bc[2 * a] == TSLB_BC_PERIODIC;
+    g.N = (long long)p->nx * p->ny * p->nz;
+    g.ld = (long long)plane_elems(g.N);
+    double U = p->u_scale > 0.0 ? p->u_scale : 0.05;
+    if (p->storage == TSLB_STORE_FP32) U = 1.0;
+    sc.s1 = (float)U;
+    sc.s2 = (float)(U * U);
+    sc.inv_s1 = (float)(1.0 / U);
+    sc.inv_s2 = (float)(1.0 / (U * U));
+}
+
+size_t ctx_device_bytes(const tslb_ctx *c) {
+    const size_t ld = (size_t)c->geo.ld;
+    size_t b = 2 * c->buffer_bytes;
+    b += c->scratch.partial_blocks * (2 * sizeof(double) + sizeof(long long)) + 2 * sizeof(double) + sizeof(long long);
+    if (c->scratch.stage) b += 11 * ld * sizeof(float);
+    if (c->scratch.geo) b += 9 * ld * sizeof(float);
+    if (c->stats.sum) b += 5 * ld * sizeof(double);
+    return b;
+}
 }  // namespace tslb
 
 // A context that is a member of a serving group is advanced by the group; every
@@ -165,11 +226,8 @@ int tslb_create(const tslb_params *p, tslb_ctx **out) {
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
             c->cu_count = cus;
     }
-    Geo &g = c->geo;
-    g.nx = p->nx; g.ny = p->ny; g.nz = p->nz;
-    for (int a = 0; a < 3; ++a) g.per[a] = p->bc[2 * a] == TSLB_BC_PERIODIC;
-    g.N = (long long)p->nx * p->ny * p->nz;
-    g.ld = (long long)plane_elems(g.N);
+    derive_layout(p, c->geo, c->scales);
+    const Geo &g = c->geo;
     c->has_boundary = !(g.per[0] && g.per[1] && g.per[2]);
     Phys &ph = c->phys;
     ph.omega = (float)(1.0 / (3.0 * p->nu + 0.5));
@@ -182,12 +240,6 @@ int tslb_create(const tslb_params *p, tslb_ctx **out) {
     ph.inlet_noise = (float)p->inlet_noise;
     ph.noise_key = splitmix_finalise(p->seed + 0x9e3779b97f4a7c15ULL);
     for (int s = 0; s < 6; ++s) ph.bc[s] = p->bc[s];
-    double U = p->u_scale > 0.0 ? p->u_scale : 0.05;
-    if (c->storage == TSLB_STORE_FP32) U = 1.0;
-    c->scales.s1 = (float)U;
-    c->scales.s2 = (float)(U * U);
-    c->scales.inv_s1 = (float)(1.0 / U);
-    c->scales.inv_s2 = (float)(1.0 / (U * U));
     c->buffer_bytes = state_buffer_bytes(g.N, c->storage, c->phase);
     size_t need = 2 * c->buffer_bytes;
     if (p->device_buffer) {
@@ -248,18 +300,37 @@ int tslb_set_state(tslb_ctx *c, const float *rho_dev, const float *u, const floa
     ON_DEVICE(c);
     if (!rho_dev || !u || !pi_neq || (!phi && c->phase)) return fail(c, TSLB_E_INVAL, "every field is required");
     if (step < 0) return fail(c, TSLB_E_INVAL, "step must be >= 0");
-    int rc = ensure_planes(c);
+    int rc = ensure_planes(c, true, true);
     if (rc) return rc;
     const size_t N = (size_t)c->geo.N, ld = (size_t)c->geo.ld;
     float *st = c->scratch.stage;
-    HIP_TRY(c, hipMemcpyAsync(st, rho_dev, N * 4, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpy2DAsync(st + ld, ld * 4, u, N * 4, N * 4, 3, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpy2DAsync(st + 4 * ld, ld * 4, pi_neq, N * 4, N * 4, 6, hipMemcpyHostToDevice, c->stream));
-    if (c->phase) HIP_TRY(c, hipMemcpyAsync(st + 10 * ld, phi, N * 4, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, launch_set_state(c, st, c->scratch.geo, c->buf[c->cur], c->stream));
+    hipError_t e = hipMemcpyAsync(st, rho_dev, N * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpy2DAsync(st + ld, ld * 4, u, N * 4, N * 4, 3, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(st + 4 * ld, ld * 4, pi_neq, N * 4, N * 4, 6, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && c->phase) e = hipMemcpyAsync(st + 10 * ld, phi, N * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_set_state(c, st, c->scratch.geo, c->buf[c->cur], c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    rc = release_planes(c);
+    if (e != hipSuccess) return fail(c, TSLB_E_DEVICE, std::string("set state: ") + hipGetErrorString(e));
+    if (rc) return rc;
+    c->step = step;
+    c->state_set = true;
+    c->mass_ref_set = false;
+    return TSLB_OK;
+}
+
+int tslb_set_state_rest(tslb_ctx *c, int64_t step) {
+    if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    NOT_IN_GROUP(c);
+    ON_DEVICE(c);
+    if (step < 0) return fail(c, TSLB_E_INVAL, "step must be >= 0");
+    // rho' = 0, ubar = 0, Q = 0 and phi = 0 are all-zero words in every storage type
+    HIP_TRY(c, hipMemsetAsync(c->buf[c->cur].mom, 0, c->buffer_bytes, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->step = step;
     c->state_set = true;
+    c->mass_ref_set = false;
     return TSLB_OK;
 }
 
@@ -269,7 +340,7 @@ int tslb_step(tslb_ctx *c, int64_t nsteps) {
     ON_DEVICE(c);
     if (nsteps < 0) return fail(c, TSLB_E_INVAL, "nsteps must be >= 0");
     if (!c->state_set) return fail(c, TSLB_E_STATE, "no state: call tslb_set_state first");
-    int rc = c->kernel == TSLB_KERNEL_GATHER ? ensure_planes(c) : TSLB_OK;
+    int rc = ensure_planes(c, false, c->kernel == TSLB_KERNEL_GATHER || c->stats.every > 0);
     if (rc) return rc;
     StepTimer &tm = c->timer;
     const size_t max_timed = 8192;
@@ -292,6 +363,20 @@ int tslb_step(tslb_ctx *c, int64_t nsteps) {
     // current state's layers are filled once here (the fill is idempotent).
     const bool fused = c->kernel == TSLB_KERNEL_FUSED;
     if (fused && nsteps > 0) HIP_TRY(c, launch_boundary(c, c->buf[c->cur], c->step, c->stream));
+    // the mass bound is relative to the mass of the state stepping started from
+    const bool mass_check = c->p.check_interval > 0 && c->p.max_mass_drift > 0.0;
+    if (mass_check && nsteps > 0 && !c->mass_ref_set) {
+        double d[2];
+        long long phi_sum;
+        if (!fused) {
+            rc = fill_boundary_now(c);
+            if (rc) return rc;
+        }
+        rc = run_diagnostics(c, d, &phi_sum);
+        if (rc) return rc;
+        c->mass_ref = (double)c->geo.N + d[0];
+        c->mass_ref_set = true;
+    }
     for (int64_t s = 0; s < nsteps; ++s) {
         if (!fused) HIP_TRY(c, launch_boundary(c, c->buf[c->cur], c->step, c->stream));
         bool timing = tm.enabled && timed < max_timed;
@@ -321,6 +406,17 @@ int tslb_step(tslb_ctx *c, int64_t nsteps) {
                 std::snprintf(msg, sizeof msg, "non-finite state at step %lld", (long long)c->step);
                 return fail(c, TSLB_E_UNSTABLE, msg);
             }
+            if (mass_check) {
+                const double mass = (double)c->geo.N + d[0];
+                const double drift = std::fabs(mass - c->mass_ref) / std::fabs(c->mass_ref);
+                if (!(drift <= c->p.max_mass_drift)) {
+                    tm.used = timed;
+                    char msg[200];
+                    std::snprintf(msg, sizeof msg, "mass drifted by %.3e (relative, bound %.3e) at step %lld", drift,
+                                  c->p.max_mass_drift, (long long)c->step);
+                    return fail(c, TSLB_E_UNSTABLE, msg);
+                }
+            }
         }
     }
     if (tm.enabled) tm.used = timed;
@@ -340,20 +436,22 @@ int tslb_moments(tslb_ctx *c, float *rho_dev, float *u, float *pi_neq) {
     NOT_IN_GROUP(c);
     ON_DEVICE(c);
     if (!c->state_set) return fail(c, TSLB_E_STATE, "no state");
-    int rc = ensure_planes(c);
+    int rc = fill_boundary_now(c);
     if (rc) return rc;
-    rc = fill_boundary_now(c);
+    rc = ensure_planes(c, true, true);
     if (rc) return rc;
     const size_t N = (size_t)c->geo.N, ld = (size_t)c->geo.ld;
     float *st = c->scratch.stage;
-    HIP_TRY(c, launch_geometry(c, c->buf[c->cur].phi, c->scratch.geo, c->stream));
-    HIP_TRY(c, launch_readout(c, c->buf[c->cur], c->scratch.geo, st, c->stream));
-    if (rho_dev) HIP_TRY(c, hipMemcpyAsync(rho_dev, st, N * 4, hipMemcpyDeviceToHost, c->stream));
-    if (u) HIP_TRY(c, hipMemcpy2DAsync(u, N * 4, st + ld, ld * 4, N * 4, 3, hipMemcpyDeviceToHost, c->stream));
-    if (pi_neq)
-        HIP_TRY(c, hipMemcpy2DAsync(pi_neq, N * 4, st + 4 * ld, ld * 4, N * 4, 6, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    return TSLB_OK;
+    hipError_t e = launch_geometry(c, c->buf[c->cur].phi, c->scratch.geo, c->stream);
+    if (e == hipSuccess) e = launch_readout(c, c->buf[c->cur], c->scratch.geo, st, c->stream);
+    if (e == hipSuccess && rho_dev) e = hipMemcpyAsync(rho_dev, st, N * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && u) e = hipMemcpy2DAsync(u, N * 4, st + ld, ld * 4, N * 4, 3, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && pi_neq)
+        e = hipMemcpy2DAsync(pi_neq, N * 4, st + 4 * ld, ld * 4, N * 4, 6, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    rc = release_planes(c);
+    if (e != hipSuccess) return fail(c, TSLB_E_DEVICE, std::string("readout: ") + hipGetErrorString(e));
+    return rc;
 }
 
 int tslb_phase(tslb_ctx *c, float *phi) {
@@ -382,6 +480,8 @@ int tslb_phase(tslb_ctx *c, float *phi) {
 
 size_t tslb_state_bytes(const tslb_ctx *c) { return c ? c->buffer_bytes : 0; }
 
+size_t tslb_device_bytes(const tslb_ctx *c) { return c ? ctx_device_bytes(c) : 0; }
+
 int tslb_get_state_raw(tslb_ctx *c, void *host, size_t bytes) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
     NOT_IN_GROUP(c);
@@ -405,6 +505,7 @@ int tslb_set_state_raw(tslb_ctx *c, const void *host, size_t bytes, int64_t step
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->step = step;
     c->state_set = true;
+    c->mass_ref_set = false;
     return TSLB_OK;
 }
 
@@ -455,6 +556,26 @@ double tslb_last_step_kernel_ms(tslb_ctx *c) {
         total += ms;
     }
     return total / (double)c->timer.used;
+}
+
+int tslb_step_kernel_times(tslb_ctx *c, float *ms, int64_t cap, int64_t *count) {
+    if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    if (cap < 0 || (cap > 0 && !ms) || !count) return fail(c, TSLB_E_INVAL, "bad output arguments");
+    ON_DEVICE(c);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int64_t n = (int64_t)c->timer.used;
+    for (int64_t k = 0; k < n && k < cap; ++k)
+        HIP_TRY(c, hipEventElapsedTime(&ms[k], c->timer.ev[2 * k], c->timer.ev[2 * k + 1]));
+    *count = n;
+    return TSLB_OK;
+}
+
+int tslb_device_memory(int32_t device, size_t *free_bytes, size_t *total_bytes) {
+    if (!free_bytes || !total_bytes) return fail(nullptr, TSLB_E_INVAL, "output pointers are required");
+    hipError_t e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipMemGetInfo(free_bytes, total_bytes);
+    if (e != hipSuccess) return fail(nullptr, TSLB_E_DEVICE, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
+    return TSLB_OK;
 }
 
 int tslb_copy_bandwidth(int device, size_t bytes, int iters, double *gbps, double *ms) {
@@ -508,7 +629,7 @@ int tslb_stats_start(tslb_ctx *c, int32_t every) {
     NOT_IN_GROUP(c);
     ON_DEVICE(c);
     if (every < 1) return fail(c, TSLB_E_INVAL, "every must be >= 1");
-    int rc = ensure_planes(c);
+    int rc = ensure_planes(c, false, true);
     if (rc) return rc;
     const size_t bytes = 5 * (size_t)c->geo.ld * sizeof(double);
     if (!c->stats.sum) {
@@ -524,8 +645,9 @@ int tslb_stats_start(tslb_ctx *c, int32_t every) {
 int tslb_stats_stop(tslb_ctx *c) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
     NOT_IN_GROUP(c);
+    ON_DEVICE(c);
     c->stats.every = 0;
-    return TSLB_OK;
+    return release_planes(c);
 }
 
 int tslb_stats_get(tslb_ctx *c, float *mean_phi, float *mean_u, float *rms_uz, int64_t *samples) {

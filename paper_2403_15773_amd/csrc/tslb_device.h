@@ -179,7 +179,15 @@ constexpr float kPhiUlp = 1.0f / (float)(1 << kPhiFrac);   // 2^-30
 constexpr float kPhiInvUlp = (float)(1 << kPhiFrac);       // 2^30
 constexpr float kPhiMin = -0.45f, kPhiMax = 1.45f;
 
+// The clamp bounds on the fixed-point grid.  Every stored phase value lies in
+// [kPhiLo, kPhiHi], so a difference of two of them, (1.45 + 0.45) 2^30 at most,
+// never overflows int32; a diverging run saturates there instead.
+constexpr int32_t kPhiLo = (int32_t)(-0.45 * (double)(1 << kPhiFrac));
+constexpr int32_t kPhiHi = (int32_t)(1.45 * (double)(1 << kPhiFrac));
+
 __host__ __device__ inline float phi_to_float(int32_t v) { return (float)v * kPhiUlp; }
+
+__device__ __forceinline__ int32_t phi_clamp(int32_t v) { return min(max(v, kPhiLo), kPhiHi); }
 
 // Round to the nearest representable value, clamped to [kPhiMin, kPhiMax].
 __device__ __forceinline__ int32_t phi_from_float(float v) {

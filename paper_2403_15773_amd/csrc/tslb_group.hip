@@ -34,7 +34,9 @@ struct tslb_group {
     std::vector<Member> members;  // in admission order
     FusedDomain *h_tab[kRing] = {};
     FusedDomain *d_tab[kRing] = {};
-    hipEvent_t ev[kRing] = {};
+    hipEvent_t ev[kRing] = {};     // end of launch (slot reuse and retirement)
+    hipEvent_t ev_start[kRing] = {};  // start of launch (device-busy time)
+    double busy_ms = 0.0;          // summed durations of the completed launches
     int64_t slot_launch[kRing] = {-1, -1, -1, -1};
     int64_t launches = 0;        // launches issued
     int64_t completed = -1;      // every launch <= completed has finished
@@ -71,6 +73,10 @@ int refresh_completed(tslb_group *g) {
         const hipError_t q = hipEventQuery(g->ev[slot]);
         if (q == hipErrorNotReady) break;
         if (q != hipSuccess) return gfail(g, TSLB_E_DEVICE, std::string("hipEventQuery: ") + hipGetErrorString(q));
+        float ms = 0.f;
+        const hipError_t e = hipEventElapsedTime(&ms, g->ev_start[slot], g->ev[slot]);
+        if (e != hipSuccess) return gfail(g, TSLB_E_DEVICE, std::string("hipEventElapsedTime: ") + hipGetErrorString(e));
+        g->busy_ms += ms;
         g->completed = next;
     }
     return TSLB_OK;
@@ -79,6 +85,7 @@ int refresh_completed(tslb_group *g) {
 void release_all(tslb_group *g) {
     for (int s = 0; s < tslb_group::kRing; ++s) {
         if (g->ev[s]) (void)hipEventDestroy(g->ev[s]);
+        if (g->ev_start[s]) (void)hipEventDestroy(g->ev_start[s]);
         if (g->d_tab[s]) (void)hipFree(g->d_tab[s]);
         if (g->h_tab[s]) (void)hipHostFree(g->h_tab[s]);
     }
@@ -123,7 +130,8 @@ int tslb_group_create(size_t hbm_budget_bytes, int32_t max_domains, void *stream
     for (int s = 0; e == hipSuccess && s < tslb_group::kRing; ++s) {
         e = hipHostMalloc((void **)&g->h_tab[s], tab, hipHostMallocDefault);
         if (e == hipSuccess) e = hipMalloc((void **)&g->d_tab[s], tab);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&g->ev[s], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreate(&g->ev[s]);
+        if (e == hipSuccess) e = hipEventCreate(&g->ev_start[s]);
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&g->admit_ev, hipEventDisableTiming);
     if (e == hipSuccess) {
@@ -154,7 +162,7 @@ int tslb_group_admit(tslb_group *g, tslb_ctx *c, int64_t nsteps) {
     if (c->p.device != g->device) return gfail(g, TSLB_E_INVAL, "ctx and group are on different devices");
     if ((int)g->members.size() >= g->max_domains) return gfail(g, TSLB_E_NOMEM, "all domain slots are taken");
     GHIP_TRY(g, hipSetDevice(g->device));
-    const size_t bytes = 2 * c->buffer_bytes;
+    const size_t bytes = ctx_device_bytes(c);
     if (g->bytes_in_use + bytes > g->budget) return gfail(g, TSLB_E_NOMEM, "HBM budget exhausted");
     try {
         g->members.reserve(g->members.size() + 1);
@@ -238,6 +246,7 @@ int tslb_group_poll(tslb_group *g, tslb_ctx **done, int32_t cap, int32_t *ndone)
             ++count[cl];
         }
     }
+    GHIP_TRY(g, hipEventRecord(g->ev_start[slot], g->stream));
     GHIP_TRY(g, hipMemcpyAsync(g->d_tab[slot], h, (size_t)nrec * sizeof(FusedDomain), hipMemcpyHostToDevice,
                                g->stream));
     for (int cl = 0; cl < kClasses; ++cl)
@@ -262,6 +271,16 @@ int tslb_group_status(const tslb_group *g, size_t *bytes_in_use, int32_t *member
     if (bytes_in_use) *bytes_in_use = g->bytes_in_use;
     if (members) *members = (int32_t)g->members.size();
     if (launches) *launches = g->launches;
+    return TSLB_OK;
+}
+
+int tslb_group_busy(tslb_group *g, double *busy_ms, int64_t *completed) {
+    if (!g) return gfail(nullptr, TSLB_E_INVAL, "group is NULL");
+    GHIP_TRY(g, hipSetDevice(g->device));
+    int rc = refresh_completed(g);
+    if (rc) return rc;
+    if (busy_ms) *busy_ms = g->busy_ms;
+    if (completed) *completed = g->completed + 1;
     return TSLB_OK;
 }
 

@@ -72,6 +72,8 @@ struct tslb_ctx {
     int cur = 0;
     int64_t step = 0;
     bool state_set = false;
+    bool mass_ref_set = false;  // mass_ref taken since the last state was set
+    double mass_ref = 0.0;      // mass when stepping started (max_mass_drift)
     hipStream_t stream = nullptr;
     bool owns_stream = false;
     tslb::Scratch scratch;
@@ -91,7 +93,15 @@ void set_thread_error(const std::string &msg);
 // Remove a member from its group (waits for the group's queued work).
 void group_detach(tslb_group *g, tslb_ctx *c);
 
+// Parameter checks of tslb_create (false with the reason in why).
+bool validate_params(const tslb_params *p, std::string &why);
+// Lattice geometry and storage scales of a validated parameter set.
+void derive_layout(const tslb_params *p, Geo &g, Scales &sc);
+
 size_t plane_elems(long long N);
+// Device memory a context holds now: its two state buffers (caller-owned or
+// not), the diagnostics partials and any scratch planes currently allocated.
+size_t ctx_device_bytes(const tslb_ctx *c);
 size_t state_buffer_bytes(long long N, int storage, bool phase);
 
 // Launchers (all asynchronous on `s`); each returns the hipError_t of the launch.
@@ -117,6 +127,13 @@ hipError_t launch_step_fused_multi(const FusedDomain *doms, int ndom, int total_
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
 hipError_t launch_diagnostics(const tslb_ctx *c, StateView st, const Scratch &sc, hipStream_t s);
 size_t diagnostics_blocks(const tslb_ctx *c);
+// The same two diagnostics kernels for any state buffer of geometry g: per-block
+// partials (sum rho', finite probe; sum of fixed-point phi) of `blocks` blocks,
+// then their fixed-order total in result[0..1] and *result_i.
+hipError_t launch_diagnostics_raw(const Geo &g, const Scales &sc, int storage, StateView st, double *partial,
+                                  long long *partial_i, int blocks, double *result, long long *result_i,
+                                  hipStream_t s);
+int diagnostics_blocks_for(long long N);
 // Add phi, u (= ubar + F/(2 rho), F from geo) and u_z^2 of every node of st to the sums.
 hipError_t launch_stats_accum(const tslb_ctx *c, StateView st, const float *geo, double *sum, hipStream_t s);
 

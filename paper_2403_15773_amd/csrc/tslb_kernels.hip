@@ -395,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void k_step_gather(Geo g, Phys ph, Scales s
     m[8] = acc[8] - acc[1] * acc[3] * inv;
     m[9] = acc[9] - acc[2] * acc[3] * inv;
     store_raw<ST>(out, g, sc, id, m);
-    if (out.phi) out.phi[id] = phin;
+    if (out.phi) out.phi[id] = phi_clamp(phin);
 }
 
 // ---- launchers ----
@@ -454,10 +454,12 @@ hipError_t launch_step_gather(const tslb_ctx *c, StateView in, const float *geo,
     return hipGetLastError();
 }
 
-size_t diagnostics_blocks(const tslb_ctx *c) {
-    long long b = grid_for(c->geo.N);
-    return (size_t)(b < 1024 ? b : 1024);
+int diagnostics_blocks_for(long long N) {
+    long long b = grid_for(N);
+    return (int)(b < 1024 ? b : 1024);
 }
+
+size_t diagnostics_blocks(const tslb_ctx *c) { return (size_t)diagnostics_blocks_for(c->geo.N); }
 
 hipError_t launch_stats_accum(const tslb_ctx *c, StateView st, const float *geo, double *sum, hipStream_t s) {
     TSLB_DISPATCH(c->storage, k_stats_accum, dim3(grid_for(c->geo.N)), dim3(kBlock), 0, s, c->geo, c->scales, st, geo,
@@ -465,14 +467,19 @@ hipError_t launch_stats_accum(const tslb_ctx *c, StateView st, const float *geo,
     return hipGetLastError();
 }
 
-hipError_t launch_diagnostics(const tslb_ctx *c, StateView st, const Scratch &sc, hipStream_t s) {
-    TSLB_DISPATCH(c->storage, k_diag_partial, dim3((unsigned)sc.partial_blocks), dim3(kBlock), 0, s, c->geo,
-                  c->scales, st, sc.partial, sc.partial_i);
+hipError_t launch_diagnostics_raw(const Geo &g, const Scales &sc, int storage, StateView st, double *partial,
+                                  long long *partial_i, int blocks, double *result, long long *result_i,
+                                  hipStream_t s) {
+    TSLB_DISPATCH(storage, k_diag_partial, dim3((unsigned)blocks), dim3(kBlock), 0, s, g, sc, st, partial, partial_i);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kBlock), 0, s, sc.partial, sc.partial_i, (int)sc.partial_blocks,
-                       sc.result, sc.result_i);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kBlock), 0, s, partial, partial_i, blocks, result, result_i);
     return hipGetLastError();
+}
+
+hipError_t launch_diagnostics(const tslb_ctx *c, StateView st, const Scratch &sc, hipStream_t s) {
+    return launch_diagnostics_raw(c->geo, c->scales, c->storage, st, sc.partial, sc.partial_i,
+                                  (int)sc.partial_blocks, sc.result, sc.result_i, s);
 }
 
 }  // namespace tslb

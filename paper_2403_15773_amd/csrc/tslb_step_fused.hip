@@ -591,7 +591,8 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
                     m[7] = fmaf(-jx * inv, jy, Hxy);
                     m[8] = fmaf(-jx * inv, jz, m10.m1);
                     m[9] = fmaf(-jy * inv, jz, m01.m1);
-                    const int32_t phin = PA + pdown;
+                    // streamed phase, held to the clamp range (a stable run never reaches it)
+                    const int32_t phin = phi_clamp(PA + pdown);
                     // the z walls of this column take the values of planes 1 and nz-2
                     // (x_F of an edge node is interior in every coordinate, so the
                     // image is made from the moments before any x/y rule)
@@ -697,14 +698,10 @@ __global__ __launch_bounds__(NT) void k_step_fused_multi(const FusedDomain *__re
 
 // z planes per workgroup: the fixed choice of tslb_set_kernel, else the chunk
 // length that minimises a compute unit's share of the work.  A workgroup on a
-// chunk of lz planes runs lz + 6 pipeline iterations (the prologue refills the
-// three-plane rings), and the W = tiles * ceil(nz / lz) workgroups spread over
-// the compute units, ceil(W / CUs) per unit, so the cost is
-// ceil(W / CUs) * (lz + 6).  Long chunks recompute less halo; short ones keep
-// every unit busy.  Ties go to the shorter chunk.
-// Chunk length of a lattice: a workgroup on a chunk of lz planes walks lz + 6
-// planes (the pipeline), and the W work items give each CU ceil(W / CUs) of
-// them, so the cost is ceil(W / CUs) (lz + 6).  Chunks are at most kMaxChunk
+// chunk of lz planes walks lz + 6 planes (the pipeline refills its rings), and
+// the W work items give each CU ceil(W / CUs) of them, so the cost is
+// ceil(W / CUs) (lz + 6): long chunks recompute less halo, short ones keep
+// every unit busy; ties go to the shorter chunk.  Chunks are at most kMaxChunk
 // planes: workgroups that share halo columns run side by side, but over a long
 // chunk they drift apart in z and their shared halo planes leave L2 before
 // the neighbour reads them (HBM reads 1.48x the state at 2048 planes on a

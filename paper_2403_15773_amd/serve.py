@@ -2,16 +2,18 @@
 
 Requests (cubic boxes of different sizes, droplet or jet set-ups, different
 Re and We) arrive as a Poisson process.  The loop admits arrived requests in
-FIFO order while the HBM budget and the domain slots allow, and every poll of
+FIFO order while the HBM budget (by default the device's free memory when the
+stream starts, less a reserve) and the domain slots allow, and every poll of
 the group launches one step of all admitted requests together (one
 multi-domain kernel launch), so requests that arrive while others run share
 the device from their first step on.  A request's latency is the time from its
 arrival to its retirement; throughput is the total node updates over the
 makespan.
 
-The loop talks to a backend with five calls (``required_bytes``, ``create``,
-``admit``, ``poll``, ``finish``); :class:`GpuBackend` drives the C-ABI group
-(``tslb_group_*``).  Nothing here computes any part of the method.
+The loop talks to a backend with a few calls (``required_bytes``, ``create``,
+``admit``, ``poll``, ``finish``, and ``admission_budget`` when no budget is
+given); :class:`GpuBackend` drives the C-ABI group (``tslb_group_*``).
+Nothing here computes any part of the method.
 """
 from __future__ import annotations
 
@@ -105,18 +107,23 @@ def _create(backend, req, prepared):
     return backend.create(req, prepared.result())
 
 
-def serve(requests, backend, budget_bytes, max_domains=64, clock=time.perf_counter, sleep=time.sleep,
+def serve(requests, backend, budget_bytes=None, max_domains=64, clock=time.perf_counter, sleep=time.sleep,
           prepare_workers=4, on_done=None):
     """Run the stream; return one Record per request (in request order).
 
     Arrived requests wait in a FIFO queue; the head is admitted when its state
     bytes fit the budget next to the running ones and a slot is free (a head
-    that does not fit blocks the queue: no overtaking).  Host-side initial
-    fields are prepared by a thread pool as requests arrive.  Creating a
-    request's lattice (device allocation, upload of its fields) and finishing
-    a retired one (diagnostics, release) run on one worker thread, so the loop
-    that keeps the device's launch queue filled never waits for them; lattices
-    are admitted in the order their creation started."""
+    that does not fit blocks the queue: no overtaking).  budget_bytes None
+    takes ``backend.admission_budget()`` (the device's free memory less a
+    reserve).  Host-side initial fields are prepared by a thread pool as
+    requests arrive.  Creating a request's lattice (device allocation, upload
+    of its fields) and finishing a retired one (diagnostics, release) run on
+    one worker thread, so the loop that keeps the device's launch queue filled
+    never waits for them.  Lattices are admitted in the order their creation
+    started: one the device refuses stays first in line and is offered again
+    after the next poll, and no later lattice is admitted before it."""
+    if budget_bytes is None:
+        budget_bytes = backend.admission_budget()
     pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
     queue = collections.deque()
     recs = {r.id: Record(r) for r in requests}
@@ -124,6 +131,7 @@ def serve(requests, backend, budget_bytes, max_domains=64, clock=time.perf_count
     creating = collections.deque()  # (request, bytes, future of the handle), FIFO
     finishing = []       # (Record, future of the finish info)
     in_use = 0
+    idle_refusals = 0
     pool = ThreadPoolExecutor(max_workers=max(1, prepare_workers))
     worker = ThreadPoolExecutor(max_workers=1)
     futures = {}
@@ -159,14 +167,18 @@ def serve(requests, backend, budget_bytes, max_domains=64, clock=time.perf_count
                 in_use += need
                 creating.append((r, need, worker.submit(_create, backend, r, futures.pop(r.id))))
             while creating and creating[0][2].done():
-                r, need, fut = creating.popleft()
+                r, need, fut = creating[0]
                 h = fut.result()
-                if not backend.admit(h, r.steps):  # the device refused: retry from the head of the queue
-                    backend.discard(h)
-                    in_use -= need
-                    queue.appendleft(r)
-                    futures[r.id] = pool.submit(backend.prepare, r)
+                if not backend.admit(h, r.steps):
+                    # the device refused (its own budget or slots): the lattice keeps
+                    # its place and is offered again after members retire; an idle
+                    # device that refuses it twice never will take it
+                    idle_refusals = idle_refusals + 1 if not active else 0
+                    if idle_refusals >= 2:
+                        raise RuntimeError("request %d was refused by an idle device" % r.id)
                     break
+                idle_refusals = 0
+                creating.popleft()
                 recs[r.id].admitted = clock() - t0
                 active[backend.key(h)] = (recs[r.id], need)
             if active:
@@ -187,11 +199,14 @@ def serve(requests, backend, budget_bytes, max_domains=64, clock=time.perf_count
     return [recs[r.id] for r in requests]
 
 
-def summarise(records):
-    """p50/p99 latency (s), makespan, aggregate GLUPS and counts."""
+def summarise(records, busy_s=None):
+    """p50/p99 latency (s), makespan, aggregate GLUPS, the offered load (node
+    updates requested per second of arrivals), counts and, given the device's
+    busy seconds, the fraction of the makespan the device was busy."""
     lat = np.array([r.latency for r in records], np.float64)
     start = min(r.req.arrival for r in records)
     end = max(r.done for r in records)
+    last_arrival = max(r.req.arrival for r in records)
     updates = float(sum(r.req.L ** 3 * r.req.steps for r in records))
     span = end - start
     return {
@@ -202,6 +217,8 @@ def summarise(records):
         "makespan_s": float(span),
         "node_updates": updates,
         "aggregate_glups": updates / span / 1e9 if span > 0 else math.nan,
+        "offered_glups": updates / (last_arrival - start) / 1e9 if last_arrival > start else math.nan,
+        "device_busy_frac": busy_s / span if (busy_s is not None and span > 0) else None,
         "unstable": int(sum(1 for r in records if not r.finite)),
     }
 
@@ -219,6 +236,16 @@ class GpuBackend:
     def prepare(self, req):
         return request_setup(req)
 
+    def admission_budget(self, reserve_frac=1.0 / 16):
+        """The device's free memory now, less reserve_frac of its total."""
+        free, total = self.tslb.device_memory(self.device)
+        return max(0, free - int(total * reserve_frac))
+
+    def busy_seconds(self):
+        """Summed device time of the group's completed launches."""
+        ms, _ = self.group.busy()
+        return ms * 1e-3
+
     def required_bytes(self, req):
         p, _ = request_setup_params_only(req)
         return self.tslb.required_bytes(self.tslb.make_params(**p, device=self.device))
@@ -232,9 +259,6 @@ class GpuBackend:
 
     def admit(self, sim, nsteps):
         return self.group.admit(sim, nsteps)
-
-    def discard(self, sim):
-        sim.close()
 
     def key(self, sim):
         return sim.h.value

@@ -16,7 +16,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtslb.so")
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSTABLE, E_STATE = 0, -1, -2, -3, -4, -5
 BC_PERIODIC, BC_FREESLIP, BC_INLET, BC_OUTFLOW, BC_NOSLIP = 0, 1, 2, 3, 4
@@ -30,6 +30,7 @@ EXPORTS = [
     "tslb_copy_bandwidth", "tslb_destroy", "tslb_last_error",
     "tslb_group_create", "tslb_group_admit", "tslb_group_poll", "tslb_group_status", "tslb_group_destroy",
     "tslb_group_last_error", "tslb_stats_start", "tslb_stats_stop", "tslb_stats_get", "tslb_probe_projection",
+    "tslb_set_state_rest", "tslb_step_kernel_times", "tslb_device_memory", "tslb_group_busy", "tslb_device_bytes",
 ]
 KERNEL_FUSED, KERNEL_GATHER = 0, 1
 
@@ -57,6 +58,7 @@ class Params(ctypes.Structure):
         ("device_buffer_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
         ("components", ctypes.c_int32),
+        ("max_mass_drift", ctypes.c_double),
     ]
 
 
@@ -81,11 +83,13 @@ def load_library(path: str = LIB_PATH):
             "tslb_required_bytes": (ctypes.c_size_t, [P]),
             "tslb_create": (ctypes.c_int, [P, ctypes.POINTER(vp)]),
             "tslb_set_state": (ctypes.c_int, [vp, _F, _F, _F, _F, ctypes.c_int64]),
+            "tslb_set_state_rest": (ctypes.c_int, [vp, ctypes.c_int64]),
             "tslb_step": (ctypes.c_int, [vp, ctypes.c_int64]),
             "tslb_sync": (ctypes.c_int, [vp]),
             "tslb_moments": (ctypes.c_int, [vp, _F, _F, _F]),
             "tslb_phase": (ctypes.c_int, [vp, _F]),
             "tslb_state_bytes": (ctypes.c_size_t, [vp]),
+            "tslb_device_bytes": (ctypes.c_size_t, [vp]),
             "tslb_get_state_raw": (ctypes.c_int, [vp, vp, ctypes.c_size_t]),
             "tslb_set_state_raw": (ctypes.c_int, [vp, vp, ctypes.c_size_t, ctypes.c_int64]),
             "tslb_diagnostics": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -93,6 +97,7 @@ def load_library(path: str = LIB_PATH):
             "tslb_step_index": (ctypes.c_int64, [vp]),
             "tslb_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
             "tslb_last_step_kernel_ms": (ctypes.c_double, [vp]),
+            "tslb_step_kernel_times": (ctypes.c_int, [vp, _F, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
             "tslb_set_kernel": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
             "tslb_copy_bandwidth": (ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, ctypes.c_int,
                                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
@@ -105,6 +110,9 @@ def load_library(path: str = LIB_PATH):
             "tslb_group_poll": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
             "tslb_group_status": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int32),
                                                  ctypes.POINTER(ctypes.c_int64)]),
+            "tslb_group_busy": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+            "tslb_device_memory": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t),
+                                                  ctypes.POINTER(ctypes.c_size_t)]),
             "tslb_group_destroy": (None, [vp]),
             "tslb_group_last_error": (ctypes.c_char_p, [vp]),
             "tslb_stats_start": (ctypes.c_int, [vp, ctypes.c_int32]),
@@ -121,7 +129,7 @@ def load_library(path: str = LIB_PATH):
 
 def make_params(nx, ny, nz, nu, sigma=0.0, width=3.0, gamma=0.0, eps=-1.0, bc=(0,) * 6, inlet_u=0.0,
                 inlet_d=0.0, inlet_noise=0.0, seed=0, storage="fp32", u_scale=0.0, check_interval=0, device=0,
-                device_buffer=None, device_buffer_bytes=0, stream=None, components=2) -> Params:
+                device_buffer=None, device_buffer_bytes=0, stream=None, components=2, max_mass_drift=0.0) -> Params:
     lib = load_library()
     p = Params()
     lib.tslb_params_init(ctypes.byref(p))
@@ -139,6 +147,7 @@ def make_params(nx, ny, nz, nu, sigma=0.0, width=3.0, gamma=0.0, eps=-1.0, bc=(0
     p.device_buffer_bytes = int(device_buffer_bytes)
     p.stream = stream
     p.components = int(components)
+    p.max_mass_drift = float(max_mass_drift)
     return p
 
 
@@ -150,6 +159,16 @@ def copy_bandwidth(nbytes: int, iters: int = 20, device: int = 0):
     if rc != OK:
         raise TslbError(rc, lib.tslb_last_error(None).decode())
     return g.value, m.value
+
+
+def device_memory(device: int = 0):
+    """(free, total) device memory in bytes."""
+    lib = load_library()
+    f, t = ctypes.c_size_t(), ctypes.c_size_t()
+    rc = lib.tslb_device_memory(int(device), ctypes.byref(f), ctypes.byref(t))
+    if rc != OK:
+        raise TslbError(rc, lib.tslb_last_error(None).decode())
+    return f.value, t.value
 
 
 PROJECTION_VALU, PROJECTION_MFMA = 0, 1
@@ -221,6 +240,10 @@ class Simulation:
         self._check(self.lib.tslb_set_state(self.h, rho_dev.ctypes.data_as(_F), u.ctypes.data_as(_F),
                                             P.ctypes.data_as(_F), phi_p, int(step)))
 
+    def set_state_rest(self, step=0):
+        """Fluid at rest: rho = 1, u = 0, P = 0, phi = 0 (no host transfer)."""
+        self._check(self.lib.tslb_set_state_rest(self.h, int(step)))
+
     def step(self, n=1):
         self._check(self.lib.tslb_step(self.h, int(n)))
 
@@ -249,6 +272,11 @@ class Simulation:
     def state_bytes(self):
         return self.lib.tslb_state_bytes(self.h)
 
+    @property
+    def device_bytes(self):
+        """Device memory the lattice holds now (what a serving group charges)."""
+        return self.lib.tslb_device_bytes(self.h)
+
     def get_state_raw(self) -> np.ndarray:
         buf = np.empty(self.state_bytes, np.uint8)
         self._check(self.lib.tslb_get_state_raw(self.h, buf.ctypes.data, buf.nbytes))
@@ -274,6 +302,14 @@ class Simulation:
 
     def last_step_kernel_ms(self):
         return self.lib.tslb_last_step_kernel_ms(self.h)
+
+    def step_kernel_times(self) -> np.ndarray:
+        """Per-launch fused-kernel durations (ms) of the last timed step() call."""
+        n = ctypes.c_int64()
+        self._check(self.lib.tslb_step_kernel_times(self.h, None, 0, ctypes.byref(n)))
+        out = np.empty(n.value, np.float32)
+        self._check(self.lib.tslb_step_kernel_times(self.h, out.ctypes.data_as(_F), out.size, ctypes.byref(n)))
+        return out
 
     def stats_start(self, every=1):
         """Accumulate time averages of phi, u and u_z^2 every `every` steps."""
@@ -341,6 +377,12 @@ class Group:
         b, m, l = ctypes.c_size_t(), ctypes.c_int32(), ctypes.c_int64()
         self._check(self.lib.tslb_group_status(self.h, ctypes.byref(b), ctypes.byref(m), ctypes.byref(l)))
         return {"bytes_in_use": b.value, "members": m.value, "launches": l.value}
+
+    def busy(self):
+        """(summed device time of the completed launches in ms, their count)."""
+        b, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(self.lib.tslb_group_busy(self.h, ctypes.byref(b), ctypes.byref(n)))
+        return b.value, n.value
 
     def close(self):
         if getattr(self, "h", None):

@@ -64,7 +64,8 @@ def test_defaults_and_required_bytes(lib):
 
 @pytest.mark.parametrize("field,value", [
     ("nu", 0.0), ("nu", -1.0), ("width", 0.0), ("sigma", -1e-3), ("storage", 7), ("abi_version", 99), ("components", 3), ("components", 0),
-    ("nx", 0), ("check_interval", -1), ("eps", 0.0), ("eps", 1e-40), ("eps", float("nan"))])
+    ("nx", 0), ("check_interval", -1), ("eps", 0.0), ("eps", 1e-40), ("eps", float("nan")),
+    ("max_mass_drift", -1e-6), ("max_mass_drift", float("inf"))])
 def test_invalid_parameters_rejected_on_host(lib, field, value):
     p = tslb.Params()
     lib.tslb_params_init(ctypes.byref(p))
@@ -128,8 +129,15 @@ def test_thin_axis_with_walls_rejected(lib):
 def test_null_context_calls_fail_cleanly(lib):
     assert lib.tslb_step(None, 1) == tslb.E_INVAL
     assert lib.tslb_sync(None) == tslb.E_INVAL
+    assert lib.tslb_set_state_rest(None, 0) == tslb.E_INVAL
     assert lib.tslb_step_index(None) == -1
     assert lib.tslb_state_bytes(None) == 0
+    assert lib.tslb_device_bytes(None) == 0
+    n = ctypes.c_int64(5)
+    assert lib.tslb_step_kernel_times(None, None, 0, ctypes.byref(n)) == tslb.E_INVAL
+    assert lib.tslb_group_busy(None, None, None) == tslb.E_INVAL
+    f, t = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.tslb_device_memory(0, None, ctypes.byref(t)) == tslb.E_INVAL
     lib.tslb_destroy(None)
 
 

@@ -74,8 +74,9 @@ def test_group_budget_defers_then_admits():
     sa.set_state(**fa)
     sb.set_state(**fb)
     from paper_2403_15773_amd.tslb import required_bytes
-    need = required_bytes(sa.params)  # both state buffers
-    assert need == required_bytes(sb.params) == 2 * sa.state_bytes
+    assert required_bytes(sa.params) == required_bytes(sb.params) == 2 * sa.state_bytes  # both state buffers
+    need = sa.device_bytes  # the state buffers and the diagnostics partials: what the lattice holds
+    assert need == sb.device_bytes and 2 * sa.state_bytes < need < 2 * sa.state_bytes + (1 << 20)
     with Group(hbm_budget_bytes=need + need // 2, max_domains=4) as g:
         assert g.admit(sa, a.steps)
         assert not g.admit(sb, b.steps)  # over budget: defer
@@ -92,6 +93,35 @@ def test_group_budget_defers_then_admits():
         assert g.status()["members"] == 0 and g.status()["bytes_in_use"] == 0
     sa.close()
     sb.close()
+
+
+def test_group_charge_matches_the_device_memory_a_member_holds():
+    """Admission charges what a lattice holds between calls: its state buffers
+    and diagnostics partials.  The staging and geometry planes of set-state and
+    readout are released before those calls return."""
+    from paper_2403_15773_amd.tslb import Group, Simulation, device_memory
+    _say("group charge vs device memory held")
+    r = serve.Request(0, 0.0, 128, "droplet", 1000.0, 100.0, 3, 5)
+    p, f = serve.request_setup(r)
+    with Simulation(**p) as w:  # code objects and runtime pools loaded before the measurement
+        w.set_state(**f)
+        w.moments()
+    free0, _ = device_memory(0)
+    s = Simulation(**p)
+    s.set_state(**f)
+    s.moments()
+    free1, _ = device_memory(0)
+    held = free0 - free1
+    charge = s.device_bytes
+    assert charge > 2 * s.state_bytes
+    # allocation granularity and the stream's own runtime memory: within 16 MiB
+    assert abs(held - charge) <= 16 << 20, (held, charge)
+    with Group(hbm_budget_bytes=charge, max_domains=2) as g:
+        assert g.admit(s, r.steps)
+        assert g.status()["bytes_in_use"] == charge
+        while not g.poll():
+            pass
+    s.close()
 
 
 def test_group_member_is_locked_and_zero_steps_retire():

@@ -80,9 +80,6 @@ class FakeDevice:
         self.peak_bytes = max(self.peak_bytes, sum(self.required_bytes(m["req"]) for m in self.members.values()))
         return True
 
-    def discard(self, h):
-        pass
-
     def key(self, h):
         return h["key"]
 
@@ -159,6 +156,53 @@ def test_request_larger_than_the_budget_is_an_error():
     clock = FakeClock()
     with pytest.raises(ValueError, match="more than the budget"):
         serve.serve(reqs, FakeDevice(clock), 88 * 32 ** 3, max_domains=4, clock=clock, sleep=clock.sleep)
+
+
+def test_refused_lattice_keeps_its_place():
+    """A lattice the device refuses once is offered again after the next poll,
+    before any lattice whose creation started later."""
+    reqs = serve.make_requests(10, rate=1000.0, master_seed=4, sizes=(32,), steps=(5, 10))
+    clock = FakeClock()
+
+    class RefusesOnce(FakeDevice):
+        refused = []
+
+        def admit(self, h, n):
+            rid = h["req"].id
+            if rid == 3 and not RefusesOnce.refused:
+                RefusesOnce.refused.append(rid)
+                return False
+            return super().admit(h, n)
+
+    dev = RefusesOnce(clock)
+    recs = serve.serve(reqs, dev, 10 ** 12, max_domains=4, clock=clock, sleep=clock.sleep, prepare_workers=2)
+    assert RefusesOnce.refused == [3]
+    assert dev.order == [r.id for r in sorted(reqs, key=lambda r: r.arrival)]
+    assert all(rec.extra["steps_done"] == rec.req.steps for rec in recs)
+
+
+def test_budget_defaults_to_the_backends_free_memory():
+    reqs = serve.make_requests(6, rate=100.0, master_seed=9, sizes=(32, 48), steps=(5, 8))
+    clock = FakeClock()
+
+    class Sized(FakeDevice):
+        def admission_budget(self):
+            return 88 * 48 ** 3  # one request at a time
+
+    dev = Sized(clock)
+    serve.serve(reqs, dev, None, max_domains=4, clock=clock, sleep=clock.sleep)
+    assert 0 < dev.peak_bytes <= 88 * 48 ** 3
+
+
+def test_summary_reports_offered_load_and_busy_fraction():
+    reqs = serve.make_requests(20, rate=50.0, master_seed=11, sizes=(32,), steps=(20, 40))
+    clock = FakeClock()
+    recs = serve.serve(reqs, FakeDevice(clock), 10 ** 12, max_domains=8, clock=clock, sleep=clock.sleep)
+    s = serve.summarise(recs, busy_s=0.5 * (max(r.done for r in recs) - reqs[0].arrival))
+    assert math.isclose(s["device_busy_frac"], 0.5)
+    span_arrivals = max(r.arrival for r in reqs) - min(r.arrival for r in reqs)
+    assert math.isclose(s["offered_glups"] * 1e9 * span_arrivals, sum(r.L ** 3 * r.steps for r in reqs))
+    assert serve.summarise(recs)["device_busy_frac"] is None
 
 
 # ---- the group C-ABI: argument checks only (no device is touched) ----
