@@ -10,4 +10,5 @@ routes live here:
   populations from the neighbours (the rewrite itself, Methodology Eqs. 6 and 8),
   used to check the C oracle and the equivalence the paper claims.
 """
-from .oracle import Oracle, OrcParams, build_oracle, library_path, lattice, collide, phase_collide, noise  # noqa: F401
+from .oracle import (Oracle, OrcParams, build_oracle, library_path, lattice, collide, collide_vd,  # noqa: F401
+                     phase_collide, noise)

@@ -46,6 +46,10 @@ class OrcParams(ctypes.Structure):
         ("gamma", ctypes.c_double), ("eps", ctypes.c_double),
         ("inlet_u", ctypes.c_double), ("inlet_d", ctypes.c_double), ("inlet_noise", ctypes.c_double),
         ("seed", ctypes.c_uint64),
+        ("vd", ctypes.c_int32),
+        ("rho_a", ctypes.c_double), ("rho_b", ctypes.c_double),
+        ("nu_a", ctypes.c_double), ("nu_b", ctypes.c_double),
+        ("grav", ctypes.c_double * 3),
     ]
 
 
@@ -91,6 +95,10 @@ def _load():
         lib.orc_step_count.restype = ctypes.c_long
         lib.orc_collide.argtypes = [ctypes.c_double, _D, _D, _D, ctypes.c_double, _D]
         lib.orc_collide.restype = None
+        lib.orc_collide_vd.argtypes = [ctypes.c_double, _D, _D, _D, ctypes.c_double, _D]
+        lib.orc_collide_vd.restype = None
+        lib.orc_get_accel.argtypes = [vp, _D, _D]
+        lib.orc_get_accel.restype = None
         lib.orc_phase_collide.argtypes = [ctypes.c_double, _D, _D, ctypes.c_double, _D]
         lib.orc_phase_collide.restype = None
         lib.orc_noise.argtypes = [ctypes.c_uint64] * 5
@@ -126,6 +134,18 @@ def collide(rho, u, P, F, omega):
     return f
 
 
+def collide_vd(rho, u, P, a, omega):
+    """Post-collision populations of the variable-density scheme (unit density in
+    the velocity terms, rho = 1 + p*, acceleration a) at one node (27,)."""
+    lib = _load()
+    u = np.ascontiguousarray(u, np.float64)
+    P = np.ascontiguousarray(P, np.float64)
+    a = np.ascontiguousarray(a, np.float64)
+    f = np.zeros(27)
+    lib.orc_collide_vd(float(rho), _ptr(u), _ptr(P), _ptr(a), float(omega), _ptr(f))
+    return f
+
+
 def phase_collide(phi, u, n, gamma):
     """Post-collision D3Q7 phase populations of one node (7,)."""
     lib = _load()
@@ -148,7 +168,11 @@ class Oracle:
     """One FP64 population-form lattice (periodic or with boundary layers)."""
 
     def __init__(self, nx, ny, nz, nu, sigma=0.0, width=3.0, gamma=0.0, eps=1e-12,
-                 bc=(0, 0, 0, 0, 0, 0), inlet_u=0.0, inlet_d=0.0, inlet_noise=0.0, seed=0):
+                 bc=(0, 0, 0, 0, 0, 0), inlet_u=0.0, inlet_d=0.0, inlet_noise=0.0, seed=0,
+                 rho_a=None, rho_b=None, nu_a=None, nu_b=None, gravity=(0.0, 0.0, 0.0)):
+        """rho_a/rho_b/nu_a/nu_b given: the variable-density scheme (then the
+        state's first field is rho = 1 + p*, p* the normalised pressure, and nu
+        is unused); otherwise the paper's equal-density scheme."""
         self.lib = _load()
         p = OrcParams()
         p.nx, p.ny, p.nz = nx, ny, nz
@@ -157,6 +181,12 @@ class Oracle:
         p.nu, p.sigma, p.width, p.gamma, p.eps = nu, sigma, width, gamma, eps
         p.inlet_u, p.inlet_d, p.inlet_noise = inlet_u, inlet_d, inlet_noise
         p.seed = seed
+        if rho_a is not None:
+            p.vd = 1
+            p.rho_a, p.rho_b, p.nu_a, p.nu_b = float(rho_a), float(rho_b), float(nu_a), float(nu_b)
+            for c in range(3):
+                p.grav[c] = float(gravity[c])
+        self.vd = bool(p.vd)
         h = ctypes.c_void_p()
         rc = self.lib.orc_create(ctypes.byref(p), ctypes.byref(h))
         if rc != 0:
@@ -213,6 +243,12 @@ class Oracle:
         G, n, kappa, F = self._f(3), self._f(3), self._f(), self._f(3)
         self.lib.orc_get_geometry(self.h, _ptr(G), _ptr(n), _ptr(kappa), _ptr(F))
         return {"G": G, "n": n, "kappa": kappa, "F": F}
+
+    def accel(self):
+        """(acceleration a (3, ...), omega (...)) of the current state."""
+        a, om = self._f(3), self._f()
+        self.lib.orc_get_accel(self.h, _ptr(a), _ptr(om))
+        return a, om
 
     def sums(self):
         m, p = ctypes.c_double(), ctypes.c_double()

@@ -48,6 +48,28 @@
  * the jet, has no closed form or printed value to compare with: jet physics
  * is parity unpinned (the GPU path is compared with this oracle only).
  *
+ * Variable density and viscosity (the paper's future work: both components have
+ * the same density and viscosity in its model).  Selected by params.vd = 1; the
+ * equal-density scheme above is untouched.  The scheme is the velocity-based
+ * phase-field lattice Boltzmann formulation for immiscible fluids of different
+ * density (Fakhari, Mitchell, Leonardi and Bolster, Phys. Rev. E 96, 053301,
+ * 2017), restated in the regularised Hermite form used here:
+ *   - the populations carry the normalised pressure p* and the velocity:
+ *     sum f = 1 + p*, sum f c = ubar, and the Hermite equilibrium and
+ *     regularised parts take unit density in their velocity terms,
+ *     f^eq/w = 1 + p* + c.u/c_s^2 + H2:uu/(2 c_s^4) + H3:uuu/(6 c_s^6);
+ *   - rho(phi) = rho_b + phi (rho_a - rho_b) and nu(phi) = nu_b + phi (nu_a - nu_b)
+ *     (phi clamped to [0, 1]), omega(phi) = 1/(3 nu(phi) + 1/2), per node;
+ *   - the forcing is the acceleration a = (F_s + F_p + F_mu)/rho(phi) + g, with
+ *     F_s = -sigma kappa grad(phi) (Eq. 20), the pressure force
+ *     F_p = -p* c_s^2 grad(rho) and the viscous force
+ *     F_mu = rho nu (grad u + grad u^T) . grad(rho) / rho, taken from the raw
+ *     non-equilibrium stress as F_mu = -(1 - omega/2) Q . grad(rho) with
+ *     Q = Pi - (1 + p*) c_s^2 I - ubar ubar; a = 0 on boundary layers;
+ *   - Guo's forcing at unit density: u = ubar + a/2, P = Q + a a/4.
+ * The pressure is p = rho(phi) p* c_s^2, so that at rest grad p = -sigma kappa
+ * grad(phi) and a droplet keeps Laplace's pressure jump at any density ratio.
+ *
  * Data layout: SoA, population i of node (x,y,z) at f[i*N + x + nx*(y + ny*z)].
  * Velocity i = (cx+1) + 3(cy+1) + 9(cz+1).  D3Q7 k = rest, +x, -x, +y, -y, +z, -z.
  */
@@ -72,6 +94,10 @@ typedef struct {
     double eps;             /* regulariser of |grad phi| */
     double inlet_u, inlet_d, inlet_noise;
     uint64_t seed;
+    int32_t vd;             /* 1: variable density and viscosity (see the header) */
+    double rho_a, rho_b;    /* densities of component A (phi = 1) and B (phi = 0) */
+    double nu_a, nu_b;      /* their kinematic viscosities */
+    double grav[3];         /* body acceleration g */
 } orc_params;
 
 typedef struct {
@@ -83,6 +109,7 @@ typedef struct {
     double *f, *fn, *g, *gn;                 /* populations, A/B */
     double *rho, *j, *Pi, *phi;             /* moments: rho, j (3N), Pi (6N: xx,yy,zz,xy,xz,yz), phi */
     double *G, *n, *kappa, *F;               /* geometry: G (3N), n (3N), kappa, F (3N) */
+    double *acc, *om;                        /* variable density: acceleration a (3N), omega (N) */
 } orc;
 
 /* ---- lattices (Fig. of the D3Q27 set; D3Q7 of the interface equation) ---- */
@@ -200,6 +227,42 @@ void orc_collide(double rho, const double u[3], const double Ps[6], const double
         double feq = W27[i] * rho * (1.0 + h1u / CS2 + h2uu / (2.0 * cs4) + h3uuu / (6.0 * cs6));
         double fneq = W27[i] * (h2P / (2.0 * cs4) + h3a3 / (6.0 * cs6));
         double S = W27[i] * ((cF - uF) / CS2 + cu * cF / cs4);
+        f[i] = feq + (1.0 - omega) * fneq + 0.5 * S;
+    }
+}
+
+/* The same collision with unit density in the velocity terms (variable-density
+ * scheme): f^post = w [rho + c.u/c_s^2 + H2:uu/(2 c_s^4) + H3:uuu/(6 c_s^6)]
+ * + (1 - omega) f^neq(P) + S(a)/2, rho = 1 + p*, a the acceleration. */
+void orc_collide_vd(double rho, const double u[3], const double Ps[6], const double a[3], double omega,
+                    double f[27]) {
+    lattice_init();
+    double P[3][3], a3[3][3][3];
+    sym_expand(Ps, P);
+    for (int x = 0; x < 3; ++x)
+        for (int y = 0; y < 3; ++y)
+            for (int z = 0; z < 3; ++z) a3[x][y][z] = u[x] * P[y][z] + u[y] * P[x][z] + u[z] * P[x][y];
+    const double cs4 = CS2 * CS2, cs6 = cs4 * CS2;
+    for (int i = 0; i < 27; ++i) {
+        const int *c = C27[i];
+        double h1u = 0.0, h2uu = 0.0, h3uuu = 0.0, h2P = 0.0, h3a3 = 0.0, ca = 0.0, ua = 0.0;
+        for (int x = 0; x < 3; ++x) {
+            h1u += c[x] * u[x];
+            ca += c[x] * a[x];
+            ua += u[x] * a[x];
+            for (int y = 0; y < 3; ++y) {
+                h2uu += H2T[i][x][y] * u[x] * u[y];
+                h2P += H2T[i][x][y] * P[x][y];
+            }
+        }
+        for (int m = 0; m < H3NZ[i]; ++m) {
+            int x = H3IDX[i][m][0], y = H3IDX[i][m][1], z = H3IDX[i][m][2];
+            h3uuu += H3T[i][x][y][z] * u[x] * u[y] * u[z];
+            h3a3 += H3T[i][x][y][z] * a3[x][y][z];
+        }
+        double feq = W27[i] * (rho + h1u / CS2 + h2uu / (2.0 * cs4) + h3uuu / (6.0 * cs6));
+        double fneq = W27[i] * (h2P / (2.0 * cs4) + h3a3 / (6.0 * cs6));
+        double S = W27[i] * ((ca - ua) / CS2 + h1u * ca / cs4);
         f[i] = feq + (1.0 - omega) * fneq + 0.5 * S;
     }
 }
@@ -369,9 +432,10 @@ static void boundary_values(const orc *o, int x, int y, int z, double *rho, doub
     long idF = node_index(o, v[0], v[1], v[2]);
     double r, j[3], Pi[6], ph;
     node_moments(o, o->f, o->g, idF, &r, j, Pi, &ph);
-    for (int a = 0; a < 3; ++a) ub[a] = j[a] / r;
+    const double dm = o->p.vd ? 1.0 : r;  /* density in the velocity terms */
+    for (int a = 0; a < 3; ++a) ub[a] = j[a] / dm;
     for (int s = 0; s < 6; ++s)
-        Q[s] = Pi[s] - (SYM_A[s] == SYM_B[s] ? r * CS2 : 0.0) - j[SYM_A[s]] * j[SYM_B[s]] / r;
+        Q[s] = Pi[s] - (SYM_A[s] == SYM_B[s] ? r * CS2 : 0.0) - j[SYM_A[s]] * j[SYM_B[s]] / dm;
     *rho = r;
     *phi = ph;
     switch (o->p.bc[face]) {
@@ -408,9 +472,10 @@ static void fill_boundaries(orc *o) {
                 if (!is_boundary(o, x, y, z)) continue;
                 double r, ub[3], Q[6], ph, j[3], Pi[6], f[27];
                 boundary_values(o, x, y, z, &r, ub, Q, &ph);
-                for (int a = 0; a < 3; ++a) j[a] = r * ub[a];
+                const double dm = o->p.vd ? 1.0 : r;
+                for (int a = 0; a < 3; ++a) j[a] = dm * ub[a];
                 for (int s = 0; s < 6; ++s)
-                    Pi[s] = Q[s] + (SYM_A[s] == SYM_B[s] ? r * CS2 : 0.0) + j[SYM_A[s]] * j[SYM_B[s]] / r;
+                    Pi[s] = Q[s] + (SYM_A[s] == SYM_B[s] ? r * CS2 : 0.0) + j[SYM_A[s]] * j[SYM_B[s]] / dm;
                 project_h2(r, j, Pi, f);
                 long id = node_index(o, x, y, z);
                 for (int i = 0; i < 27; ++i) o->f[(long)i * o->N + id] = f[i];
@@ -432,19 +497,87 @@ static void macroscopic(const orc *o, long id, double *rho, double u[3], double 
     *rho = r;
 }
 
+/* ---- variable density and viscosity ---- */
+
+/* rho(phi), omega(phi) of the variable-density scheme (phi clamped to [0, 1]). */
+static void vd_props(const orc *o, double phi, double *rho_phi, double *omega) {
+    double c = phi < 0.0 ? 0.0 : phi > 1.0 ? 1.0 : phi;
+    *rho_phi = o->p.rho_b + c * (o->p.rho_a - o->p.rho_b);
+    double nu = o->p.nu_b + c * (o->p.nu_a - o->p.nu_b);
+    *omega = 1.0 / (3.0 * nu + 0.5);
+}
+
+/* Acceleration of one interior node from its pressure p* = rho - 1, raw stress
+ * Q, grad(phi) G and surface-tension force Fs:
+ * a = (Fs - p* c_s^2 drho G - (1 - omega/2) drho Q.G) / rho(phi) + g. */
+static void vd_accel(const orc *o, double pstar, const double Q[6], const double G[3], const double Fs[3],
+                     double rho_phi, double omega, double a[3]) {
+    const double drho = o->p.rho_a - o->p.rho_b;
+    double Qm[3][3];
+    sym_expand(Q, Qm);
+    for (int x = 0; x < 3; ++x) {
+        double QG = Qm[x][0] * G[0] + Qm[x][1] * G[1] + Qm[x][2] * G[2];
+        double F = Fs[x] - pstar * CS2 * drho * G[x] - (1.0 - 0.5 * omega) * drho * QG;
+        a[x] = F / rho_phi + o->p.grav[x];
+    }
+}
+
+/* Per-node omega and acceleration of the current moments and geometry. */
+static void compute_accel(orc *o) {
+    const int nx = o->p.nx, ny = o->p.ny, nz = o->p.nz;
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long id = node_index(o, x, y, z);
+                double rp, om;
+                vd_props(o, o->phi[id], &rp, &om);
+                o->om[id] = om;
+                double *a = o->acc + 3 * id;
+                if (is_boundary(o, x, y, z)) {
+                    a[0] = a[1] = a[2] = 0.0;
+                    continue;
+                }
+                const double r = o->rho[id], *j = o->j + 3 * id, *Pi = o->Pi + 6 * id;
+                double Q[6];
+                for (int s = 0; s < 6; ++s)
+                    Q[s] = Pi[s] - (SYM_A[s] == SYM_B[s] ? r * CS2 : 0.0) - j[SYM_A[s]] * j[SYM_B[s]];
+                vd_accel(o, r - 1.0, Q, o->G + 3 * id, o->F + 3 * id, rp, om, a);
+            }
+}
+
+/* Guo velocity and forcing-corrected tensor at unit density (variable density):
+ * u = ubar + a/2, P = Pi - rho c_s^2 I - u u + (u a + a u)/2. */
+static void macroscopic_vd(const orc *o, long id, double *rho, double u[3], double P[6]) {
+    double r = o->rho[id];
+    const double *j = o->j + 3 * id, *a = o->acc + 3 * id, *Pi = o->Pi + 6 * id;
+    for (int x = 0; x < 3; ++x) u[x] = j[x] + 0.5 * a[x];
+    for (int s = 0; s < 6; ++s) {
+        int x = SYM_A[s], y = SYM_B[s];
+        P[s] = Pi[s] - (x == y ? r * CS2 : 0.0) - u[x] * u[y] + 0.5 * (u[x] * a[y] + a[x] * u[y]);
+    }
+    *rho = r;
+}
+
 static void step_once(orc *o) {
     const int nx = o->p.nx, ny = o->p.ny, nz = o->p.nz;
     if (o->has_bnd) fill_boundaries(o);
     compute_moments(o);
     compute_geometry(o);
+    if (o->p.vd) compute_accel(o);
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 long id = node_index(o, x, y, z);
                 double r, u[3], P[6], fp[27], gp[7];
-                macroscopic(o, id, &r, u, P);
-                orc_collide(r, u, P, o->F + 3 * id, o->omega, fp);
+                if (o->p.vd) {
+                    macroscopic_vd(o, id, &r, u, P);
+                    orc_collide_vd(r, u, P, o->acc + 3 * id, o->om[id], fp);
+                } else {
+                    macroscopic(o, id, &r, u, P);
+                    orc_collide(r, u, P, o->F + 3 * id, o->omega, fp);
+                }
                 orc_phase_collide(o->phi[id], u, o->n + 3 * id, o->gamma, gp);
                 /* push: f_i(y + c_i, t+1) = f_i^post(y, t) (Eq. 6); interior destinations only */
                 for (int i = 0; i < 27; ++i) {
@@ -502,6 +635,12 @@ static int params_valid(const orc_params *p) {
         }
     }
     double omega = 1.0 / (3.0 * p->nu + 0.5);
+    if (p->vd) {
+        if (p->vd != 1 || !(p->rho_a > 0.0) || !(p->rho_b > 0.0) || !(p->nu_a > 0.0) || !(p->nu_b > 0.0)) return 0;
+        if (!(1.0 / (3.0 * p->nu_a + 0.5) < 2.0) || !(1.0 / (3.0 * p->nu_b + 0.5) < 2.0)) return 0;
+        for (int a = 0; a < 3; ++a)
+            if (!isfinite(p->grav[a])) return 0;
+    }
     return omega < 2.0;
 }
 
@@ -510,6 +649,7 @@ void orc_free(orc *o) {
     free(o->f); free(o->fn); free(o->g); free(o->gn);
     free(o->rho); free(o->j); free(o->Pi); free(o->phi);
     free(o->G); free(o->n); free(o->kappa); free(o->F);
+    free(o->acc); free(o->om);
     free(o);
 }
 
@@ -532,8 +672,9 @@ int orc_create(const orc_params *p, orc **out) {
     o->Pi = malloc(sizeof(double) * 6 * N); o->phi = malloc(sizeof(double) * N);
     o->G = malloc(sizeof(double) * 3 * N); o->n = malloc(sizeof(double) * 3 * N);
     o->kappa = malloc(sizeof(double) * N); o->F = malloc(sizeof(double) * 3 * N);
+    o->acc = calloc(3 * (size_t)N, sizeof(double)); o->om = calloc((size_t)N, sizeof(double));
     if (!o->f || !o->fn || !o->g || !o->gn || !o->rho || !o->j || !o->Pi || !o->phi || !o->G || !o->n ||
-        !o->kappa || !o->F) {
+        !o->kappa || !o->F || !o->acc || !o->om) {
         orc_free(o);
         return ORC_ENOMEM;
     }
@@ -555,6 +696,34 @@ void orc_set_physical(orc *o, const double *rho, const double *u, const double *
     const long N = o->N;
     memcpy(o->phi, phi, sizeof(double) * N);
     compute_geometry(o);
+    if (o->p.vd) {
+        /* variable density: rho = 1 + p*.  The acceleration depends on the raw
+         * stress Q = P - a a/4 through F_mu, so (a, Q) is the fixed point of that
+         * pair, reached to rounding in a few sweeps (a is small); then
+         * ubar = u - a/2 and Pi = Q + rho c_s^2 I + ubar ubar. */
+        const int nx = o->p.nx, ny = o->p.ny;
+#pragma omp parallel for schedule(static)
+        for (long id = 0; id < N; ++id) {
+            const int x = (int)(id % nx), y = (int)((id / nx) % ny), z = (int)(id / ((long)nx * ny));
+            double r = rho[id], uu[3], Q[6], a[3] = {0, 0, 0}, j[3], Pi[6], f[27], rp, om;
+            for (int c = 0; c < 3; ++c) uu[c] = u[c * N + id];
+            vd_props(o, phi[id], &rp, &om);
+            const int bnd = is_boundary(o, x, y, z);
+            for (int it = 0; it < 4; ++it) {
+                for (int s = 0; s < 6; ++s) Q[s] = P[s * N + id] - 0.25 * a[SYM_A[s]] * a[SYM_B[s]];
+                if (!bnd) vd_accel(o, r - 1.0, Q, o->G + 3 * id, o->F + 3 * id, rp, om, a);
+            }
+            for (int s = 0; s < 6; ++s) Q[s] = P[s * N + id] - 0.25 * a[SYM_A[s]] * a[SYM_B[s]];
+            for (int c = 0; c < 3; ++c) j[c] = uu[c] - 0.5 * a[c];
+            for (int s = 0; s < 6; ++s)
+                Pi[s] = Q[s] + (SYM_A[s] == SYM_B[s] ? r * CS2 : 0.0) + j[SYM_A[s]] * j[SYM_B[s]];
+            project_h2(r, j, Pi, f);
+            for (int i = 0; i < 27; ++i) o->f[(long)i * N + id] = f[i];
+            for (int k = 0; k < 7; ++k) o->g[(long)k * N + id] = W7[k] * phi[id];
+        }
+        o->step = step;
+        return;
+    }
 #pragma omp parallel for schedule(static)
     for (long id = 0; id < N; ++id) {
         double r = rho[id], uu[3], j[3], Pi[6], f[27];
@@ -580,6 +749,7 @@ static void refresh(orc *o) {
     if (o->has_bnd) fill_boundaries(o);
     compute_moments(o);
     compute_geometry(o);
+    if (o->p.vd) compute_accel(o);
 }
 
 /* Physical moments: rho, u = (j + F/2)/rho, P = Pi - rho c_s^2 I - rho u u + (uF + Fu)/2, phi. */
@@ -589,7 +759,10 @@ void orc_get_physical(orc *o, double *rho, double *u, double *P, double *phi) {
 #pragma omp parallel for schedule(static)
     for (long id = 0; id < N; ++id) {
         double r, uu[3], Ps[6];
-        macroscopic(o, id, &r, uu, Ps);
+        if (o->p.vd)
+            macroscopic_vd(o, id, &r, uu, Ps);
+        else
+            macroscopic(o, id, &r, uu, Ps);
         if (rho) rho[id] = r;
         for (int a = 0; a < 3; ++a) if (u) u[a * N + id] = uu[a];
         for (int s = 0; s < 6; ++s) if (P) P[s * N + id] = Ps[s];
@@ -597,7 +770,8 @@ void orc_get_physical(orc *o, double *rho, double *u, double *P, double *phi) {
     }
 }
 
-/* Raw moments: rho - 1, ubar = j/rho, Q = Pi - rho c_s^2 I - j j / rho, phi. */
+/* Raw moments: rho - 1, ubar = j/rho, Q = Pi - rho c_s^2 I - j j / rho, phi (with
+ * unit density in place of rho in ubar and Q in the variable-density scheme). */
 void orc_get_raw(orc *o, double *drho, double *ub, double *Q, double *phi) {
     refresh(o);
     const long N = o->N;
@@ -605,11 +779,12 @@ void orc_get_raw(orc *o, double *drho, double *ub, double *Q, double *phi) {
     for (long id = 0; id < N; ++id) {
         double r = o->rho[id];
         const double *j = o->j + 3 * id, *Pi = o->Pi + 6 * id;
+        const double dm = o->p.vd ? 1.0 : r;
         drho[id] = r - 1.0;
-        for (int a = 0; a < 3; ++a) ub[a * N + id] = j[a] / r;
+        for (int a = 0; a < 3; ++a) ub[a * N + id] = j[a] / dm;
         for (int s = 0; s < 6; ++s) {
             int a = SYM_A[s], b = SYM_B[s];
-            Q[s * N + id] = Pi[s] - (a == b ? r * CS2 : 0.0) - j[a] * j[b] / r;
+            Q[s * N + id] = Pi[s] - (a == b ? r * CS2 : 0.0) - j[a] * j[b] / dm;
         }
         phi[id] = o->phi[id];
     }
@@ -626,6 +801,17 @@ void orc_get_geometry(orc *o, double *G, double *n, double *kappa, double *F) {
             if (F) F[a * N + id] = o->F[3 * id + a];
         }
         if (kappa) kappa[id] = o->kappa[id];
+    }
+}
+
+/* Variable-density acceleration a (3N, SoA) and omega (N) of the current state. */
+void orc_get_accel(orc *o, double *a, double *omega) {
+    refresh(o);
+    const long N = o->N;
+    for (long id = 0; id < N; ++id) {
+        for (int c = 0; c < 3; ++c)
+            if (a) a[c * N + id] = o->p.vd ? o->acc[3 * id + c] : 0.0;
+        if (omega) omega[id] = o->p.vd ? o->om[id] : o->omega;
     }
 }
 
