@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define TSLB_ABI_VERSION 3
+#define TSLB_ABI_VERSION 4
 
 enum {
     TSLB_OK = 0,
@@ -116,6 +116,31 @@ typedef struct tslb_params {
                                 from the last state set; else TSLB_E_UNSTABLE.  The method conserves
                                 mass on a closed lattice (periodic, no-slip or free-slip faces), to
                                 binary32 rounding; inlet and outflow faces exchange mass.  0 = off */
+    /* Components of different density and viscosity (the paper's model has equal
+     * ones and names this extension as future work; the Results and Conclusions
+     * sections).  variable_density = 1 selects the velocity-based phase-field form
+     * of the step for immiscible fluids of different density, in the
+     * regularised Hermite form of the rest of the step:
+     *   rho(phi) = density_b + phi (density_a - density_b), nu(phi) = nu_b + phi
+     *   (nu_a - nu_b) (phi clamped to [0, 1]; component A is phi = 1), omega per
+     *   node from nu(phi);
+     *   the first stored moment is the normalised pressure p* (pressure
+     *   p = rho(phi) p* c_s^2) instead of rho - 1, the velocity terms of the
+     *   population rebuild take unit density, and the force is the acceleration
+     *   a = (F_s + F_p + F_mu)/rho(phi) + gravity with the surface tension
+     *   F_s = -sigma kappa grad(phi) (Eq. 20), the pressure force
+     *   F_p = -p* c_s^2 grad(rho) and the viscous force
+     *   F_mu = -(1 - omega/2) Q . grad(rho) (Q the stored non-equilibrium stress);
+     *   a = 0 on boundary layers.
+     * Then rho_dev of tslb_set_state/tslb_moments is p*, u is the velocity,
+     * pi_neq is P = Q + a a/4, and the mass of tslb_diagnostics is
+     * density_b N + (density_a - density_b) sum(phi).  Requires two components,
+     * binary32 storage and the fused kernel; nu is ignored.  0 = the paper's
+     * equal-density model (gravity must then be zero). */
+    int32_t variable_density;
+    double density_a, density_b;  /* > 0 */
+    double nu_a, nu_b;            /* > 0, each with omega < 2 */
+    double gravity[3];            /* body acceleration g (finite) */
 } tslb_params;
 
 /* Fill *p with defaults: periodic 32^3, nu = 0.1, sigma = 0, W = 3, FP32, two components. */
@@ -128,16 +153,23 @@ size_t tslb_params_size(void);
  * must have.  0 if the parameters are invalid. */
 size_t tslb_required_bytes(const tslb_params *p);
 
-/* Validate p, derive omega and gamma, allocate (or adopt) device memory and bind
- * the stream.  On success *out owns the context. */
+/* Validate p, derive omega = 1/(3 nu + 1/2) (Eqs. 3-4) and gamma (Eq. 24),
+ * allocate (or adopt) device memory, zero it and bind the stream.  On success
+ * *out owns the context.  TSLB_E_INVAL (reason in tslb_last_error(NULL)),
+ * TSLB_E_NOMEM, TSLB_E_DEVICE. */
 int tslb_create(const tslb_params *p, tslb_ctx **out);
 
 /* Set the state at step `step` from physical host fields: rho_dev = rho - 1
  * (N; the deviation, because binary32 cannot resolve small density changes
  * around 1), u (3N), pi_neq (6N: the Guo-corrected non-equilibrium momentum
- * flux P), phi (N).  The stored raw state is rho - 1, ubar = u - F/(2 rho),
- * Q = P - F F/(4 rho) and phi rounded to the fixed-point grid 2^-30 (clamped to
- * [-0.45, 1.45]), with F computed from that phi.  Synchronises. */
+ * flux P), phi (N; NULL for one component).  These are the moments the method
+ * stores in place of populations (Methodology, after Eq. 7: density, velocity
+ * and the non-equilibrium momentum flux).  The stored raw state is rho - 1,
+ * ubar = u - F/(2 rho), Q = P - F F/(4 rho) and phi rounded to the fixed-point
+ * grid 2^-30 (clamped to [-0.45, 1.45]), with F the surface-tension force of
+ * Eqs. 20-21 computed from that phi (Guo's half-force shift).  Allocates and
+ * releases 80 B per node of staging planes on the device.  Synchronises.
+ * TSLB_E_INVAL for a NULL field, TSLB_E_NOMEM, TSLB_E_DEVICE. */
 int tslb_set_state(tslb_ctx *ctx, const float *rho_dev, const float *u, const float *pi_neq, const float *phi,
                    int64_t step);
 
@@ -160,11 +192,17 @@ int tslb_step(tslb_ctx *ctx, int64_t nsteps);
 /* Wait for queued work. */
 int tslb_sync(tslb_ctx *ctx);
 
-/* Physical moments at the current step: rho_dev = rho - 1 (N), u (3N),
- * pi_neq (6N); any pointer may be NULL.  Synchronises. */
+/* Physical moments at the current step, the inverse of tslb_set_state's
+ * mapping: rho_dev = rho - 1 (N), u = ubar + F/(2 rho) (3N), pi_neq =
+ * Q + F F/(4 rho) (6N), F from the current phi (Eqs. 20-21); any pointer may
+ * be NULL.  Boundary layers are filled first (Eqs. 9-10).  Allocates and
+ * releases 80 B per node of staging planes.  Synchronises.  TSLB_E_STATE before
+ * any state was set. */
 int tslb_moments(tslb_ctx *ctx, float *rho_dev, float *u, float *pi_neq);
 
-/* Phase field phi (N) at the current step.  Synchronises. */
+/* Phase field phi (N) at the current step (the order parameter of Eqs. 22-24,
+ * 1 in component A), converted from the stored fixed point.  Synchronises.
+ * TSLB_E_STATE before any state was set. */
 int tslb_phase(tslb_ctx *ctx, float *phi);
 
 /* Device memory the context holds now, in bytes: its two state buffers, the
@@ -182,7 +220,13 @@ int tslb_set_state_raw(tslb_ctx *ctx, const void *host, size_t bytes, int64_t st
 /* Conservation diagnostics of the current state: mass = sum rho (binary32
  * compensated sums per thread, binary64 across threads), phase = sum phi (exact
  * integer sum of the fixed-point field, returned as binary64), the current step
- * index and whether every stored moment is finite.  Synchronises. */
+ * index and whether every stored moment is finite.  The collision conserves
+ * mass (the zeroth moments of every correction of Eqs. 7, 16-19 and of the
+ * forcing vanish) and the phase step conserves phi (Eqs. 23-24), so on a
+ * closed lattice both stay put to rounding; the phase sum is kept exactly by
+ * the integer streaming.  With variable density the mass is
+ * density_b N + (density_a - density_b) sum(phi).  Boundary layers are filled
+ * first.  Synchronises.  TSLB_E_STATE before any state was set. */
 int tslb_diagnostics(tslb_ctx *ctx, double *mass, double *phase_sum, int64_t *step, int32_t *finite);
 
 /* Current step index (no synchronisation). */

@@ -81,6 +81,27 @@ bool validate(const tslb_params *p, std::string &why) {
         why = "max_mass_drift must be finite and >= 0";
         return false;
     }
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(p->gravity[a])) { why = "gravity must be finite"; return false; }
+    if (p->variable_density != 0 && p->variable_density != 1) { why = "variable_density must be 0 or 1"; return false; }
+    if (p->variable_density) {
+        if (p->components != 2) { why = "variable density needs two components"; return false; }
+        if (p->storage != TSLB_STORE_FP32) { why = "variable density supports binary32 storage only"; return false; }
+        if (!(p->density_a > 0.0) || !(p->density_b > 0.0) || !std::isfinite(p->density_a) ||
+            !std::isfinite(p->density_b)) {
+            why = "density_a and density_b must be positive";
+            return false;
+        }
+        const double nus[2] = {p->nu_a, p->nu_b};
+        for (double v : nus)
+            if (!(v > 0.0) || !std::isfinite(v) || !(1.0 / (3.0 * v + 0.5) < 2.0)) {
+                why = "nu_a and nu_b must be positive";
+                return false;
+            }
+    } else if (p->gravity[0] != 0.0 || p->gravity[1] != 0.0 || p->gravity[2] != 0.0) {
+        why = "gravity needs variable_density = 1";
+        return false;
+    }
     if (p->bc[4] == TSLB_BC_INLET && !(p->inlet_d > 0.0)) { why = "inlet_d must be positive"; return false; }
     return true;
 }
@@ -129,6 +150,17 @@ int release_planes(tslb_ctx *c) {
 int fill_boundary_now(tslb_ctx *c) {
     HIP_TRY(c, launch_boundary(c, c->buf[c->cur], c->step, c->stream));
     return TSLB_OK;
+}
+
+// Mass of a state from its diagnostics sums: N + sum rho' (equal densities), or
+// with variable density rho_b N + (rho_a - rho_b) sum(phi), the sum of
+// rho(phi) (exactly conserved with the phase field).
+double mass_of(const tslb_ctx *c, const double d[2], long long phi_fixed) {
+#pragma clang fp contract(off)  // products and sum rounded separately (as the no-alloc path forms them)
+    if (c->vd)
+        return c->p.density_b * (double)c->geo.N +
+               (c->p.density_a - c->p.density_b) * std::ldexp((double)phi_fixed, -kPhiFrac);
+    return (double)c->geo.N + d[0];
 }
 
 // out[0] = sum rho', out[1] = finite probe (NaN iff a stored moment is not finite),
@@ -221,6 +253,7 @@ int tslb_create(const tslb_params *p, tslb_ctx **out) {
     c->p = *p;
     c->storage = p->storage;
     c->phase = p->components == 2;
+    c->vd = p->variable_density == 1;
     {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
@@ -240,6 +273,11 @@ int tslb_create(const tslb_params *p, tslb_ctx **out) {
     ph.inlet_noise = (float)p->inlet_noise;
     ph.noise_key = splitmix_finalise(p->seed + 0x9e3779b97f4a7c15ULL);
     for (int s = 0; s < 6; ++s) ph.bc[s] = p->bc[s];
+    ph.rho_b = c->vd ? (float)p->density_b : 1.0f;
+    ph.drho = c->vd ? (float)(p->density_a - p->density_b) : 0.0f;
+    ph.nu_b = c->vd ? (float)p->nu_b : (float)p->nu;
+    ph.dnu = c->vd ? (float)(p->nu_a - p->nu_b) : 0.0f;
+    for (int a = 0; a < 3; ++a) ph.grav[a] = (float)p->gravity[a];
     c->buffer_bytes = state_buffer_bytes(g.N, c->storage, c->phase);
     size_t need = 2 * c->buffer_bytes;
     if (p->device_buffer) {
@@ -374,7 +412,7 @@ int tslb_step(tslb_ctx *c, int64_t nsteps) {
         }
         rc = run_diagnostics(c, d, &phi_sum);
         if (rc) return rc;
-        c->mass_ref = (double)c->geo.N + d[0];
+        c->mass_ref = mass_of(c, d, phi_sum);
         c->mass_ref_set = true;
     }
     for (int64_t s = 0; s < nsteps; ++s) {
@@ -407,7 +445,7 @@ int tslb_step(tslb_ctx *c, int64_t nsteps) {
                 return fail(c, TSLB_E_UNSTABLE, msg);
             }
             if (mass_check) {
-                const double mass = (double)c->geo.N + d[0];
+                const double mass = mass_of(c, d, phi_sum);
                 const double drift = std::fabs(mass - c->mass_ref) / std::fabs(c->mass_ref);
                 if (!(drift <= c->p.max_mass_drift)) {
                     tm.used = timed;
@@ -520,7 +558,7 @@ int tslb_diagnostics(tslb_ctx *c, double *mass, double *phase_sum, int64_t *step
     long long phi_fixed = 0;
     rc = run_diagnostics(c, d, &phi_fixed);
     if (rc) return rc;
-    if (mass) *mass = (double)c->geo.N + d[0];
+    if (mass) *mass = mass_of(c, d, phi_fixed);
     if (phase_sum) *phase_sum = std::ldexp((double)phi_fixed, -kPhiFrac);
     if (step) *step = c->step;
     if (finite) *finite = std::isfinite(d[1]) ? 1 : 0;
@@ -533,6 +571,8 @@ int tslb_set_kernel(tslb_ctx *c, int kernel, int chunk_z) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
     NOT_IN_GROUP(c);
     if (kernel != TSLB_KERNEL_FUSED && kernel != TSLB_KERNEL_GATHER) return fail(c, TSLB_E_INVAL, "unknown kernel");
+    if (kernel == TSLB_KERNEL_GATHER && c->vd)
+        return fail(c, TSLB_E_INVAL, "variable density runs on the fused kernel only");
     if (chunk_z < 0) return fail(c, TSLB_E_INVAL, "chunk_z must be >= 0");
     c->kernel = kernel;
     c->chunk_z = chunk_z;
@@ -629,6 +669,7 @@ int tslb_stats_start(tslb_ctx *c, int32_t every) {
     NOT_IN_GROUP(c);
     ON_DEVICE(c);
     if (every < 1) return fail(c, TSLB_E_INVAL, "every must be >= 1");
+    if (c->vd) return fail(c, TSLB_E_INVAL, "time averages are not available with variable density");
     int rc = ensure_planes(c, false, true);
     if (rc) return rc;
     const size_t bytes = 5 * (size_t)c->geo.ld * sizeof(double);

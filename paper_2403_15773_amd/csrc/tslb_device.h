@@ -38,6 +38,11 @@ struct Phys {
     float inlet_u, inlet_d, inlet_noise;
     unsigned long long noise_key;  // SplitMix64(seed)
     int bc[6];
+    // variable density and viscosity (the fused kernel's VD instantiation):
+    // rho(phi) = rho_b + drho phi, nu(phi) = nu_b + dnu phi (phi clamped to
+    // [0, 1]), body acceleration grav
+    float rho_b, drho, nu_b, dnu;
+    float grav[3];
 };
 
 // Scaled-deviation storage: value = stored * scale.  FP32 storage uses scale 1.

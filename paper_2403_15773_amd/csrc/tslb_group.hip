@@ -47,8 +47,11 @@ struct tslb_group {
 namespace {
 
 constexpr int kStorageTypes = 4;  // TSLB_STORE_FP32 .. TSLB_STORE_FP16Q
-constexpr int kClasses = 2 * kStorageTypes;  // launch classes: storage type x component count
-int class_of(const tslb_ctx *c) { return 2 * c->storage + (c->phase ? 1 : 0); }
+// launch classes: storage type x component count, plus the variable-density
+// step (binary32, two components) as a class of its own
+constexpr int kClasses = 2 * kStorageTypes + 1;
+constexpr int kClassVD = 2 * kStorageTypes;
+int class_of(const tslb_ctx *c) { return c->vd ? kClassVD : 2 * c->storage + (c->phase ? 1 : 0); }
 
 int gfail(tslb_group *g, int code, const std::string &msg) {
     if (g)
@@ -251,8 +254,9 @@ int tslb_group_poll(tslb_group *g, tslb_ctx **done, int32_t cap, int32_t *ndone)
                                g->stream));
     for (int cl = 0; cl < kClasses; ++cl)
         if (count[cl])
-            GHIP_TRY(g, launch_step_fused_multi(g->d_tab[slot] + first[cl], count[cl], work[cl], cl >> 1,
-                                                (cl & 1) != 0, g->stream));
+            GHIP_TRY(g, launch_step_fused_multi(g->d_tab[slot] + first[cl], count[cl], work[cl],
+                                                cl == kClassVD ? (int)ST_FP32 : cl >> 1,
+                                                cl == kClassVD || (cl & 1) != 0, cl == kClassVD, g->stream));
     GHIP_TRY(g, hipEventRecord(g->ev[slot], g->stream));
     g->slot_launch[slot] = id;
     g->launches = id + 1;

@@ -64,6 +64,7 @@ struct tslb_ctx {
     int storage;
     bool has_boundary;
     bool phase = true;    // two components (a phase-field plane); false: single component
+    bool vd = false;      // variable density and viscosity (velocity-based scheme)
     size_t plane_bytes;   // bytes of one moment plane (storage type)
     size_t buffer_bytes;  // bytes of one state buffer
     void *base = nullptr; // both buffers
@@ -123,7 +124,7 @@ int fused_work_items(const tslb_ctx *c, int lz);
 // One fused step of every domain of a device table (all of one storage type and
 // component count).
 hipError_t launch_step_fused_multi(const FusedDomain *doms, int ndom, int total_work, int storage, bool phase,
-                                   hipStream_t s);
+                                   bool vd, hipStream_t s);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
 hipError_t launch_diagnostics(const tslb_ctx *c, StateView st, const Scratch &sc, hipStream_t s);
 size_t diagnostics_blocks(const tslb_ctx *c);

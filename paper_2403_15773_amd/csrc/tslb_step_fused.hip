@@ -28,6 +28,14 @@
 //   destination: moments sum_i w_i H(c_i) t_i(x - c_i) as a tensor product of
 //            1-D three-point transforms written relative to the middle value, so
 //            the large isotropic part cancels before rounding.
+// Variable density and viscosity (VD): the velocity-based form of the phase-field
+// scheme for components of different density.  The stored rho' is then the
+// normalised pressure p*, the velocity terms of the rebuild take unit density,
+// omega follows nu(phi) per source, and F is replaced by the acceleration
+//   a = (-sigma kappa G - p* c_s^2 drho G - (1 - omega/2) drho Q.G) / rho(phi) + g
+// (surface tension, pressure and viscous forces over rho(phi) = rho_b + drho phi,
+// plus gravity; zero on boundary layers), so that at the destination
+// ubar = j and Q = Pi - rho c_s^2 I - j j.
 // Precision: the source builds tau = t - rho' (no density part) and publishes its
 // rho' once; the destination forms t_i - rho'(own column, same plane) as
 // tau_i + (rho'(source) - rho'(own column)), exact differences of neighbours, and
@@ -146,7 +154,7 @@ __device__ __forceinline__ int xcd_work_item(int b, int nb) {
 // MULTI marks the multi-lattice kernel's instantiation: it keeps that kernel's
 // copy of the step apart from the single-lattice kernel's, whose code is
 // otherwise changed (and slowed) by the second user of the same instantiation.
-template <int ST, bool PH, bool G, bool MULTI>
+template <int ST, bool PH, bool G, bool MULTI, bool VD = false>
 __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phys &ph, const Scales &sc,
                                            const StateView &in, const StateView &out, int lz, int tiles_x,
                                            int tiles_y, unsigned long long step_next, int w) {
@@ -336,6 +344,8 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
         if (it >= 4) {
             // ---- S3: kappa and F at the source (plane r = q - 1) ----
             float F0 = 0.f, F1 = 0.f, F2 = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
+            float Gx = 0.f, Gy = 0.f, Gz = 0.f;  // grad(phi) at the source (VD)
+            bool sbnd = false;                   // the source is a boundary-layer node (VD)
             int32_t phis = 0;
             if constexpr (PH) {
                 if (is_src) {
@@ -344,9 +354,19 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
                     const bool bnd = src_bnd_xy || (!g.per[2] && (zr <= 0 || zr >= g.nz - 1));
                     const float a = bnd ? 0.f : -sigma * kap;
                     const float *Gs = &sm.G[(it + 1) % 3][0][0];  // plane r
-                    F0 = a * Gs[sidx];
-                    F1 = a * Gs[NSRC + sidx];
-                    F2 = a * Gs[2 * NSRC + sidx];
+                    if constexpr (VD) {
+                        Gx = Gs[sidx];
+                        Gy = Gs[NSRC + sidx];
+                        Gz = Gs[2 * NSRC + sidx];
+                        sbnd = bnd;
+                        F0 = a * Gx;
+                        F1 = a * Gy;
+                        F2 = a * Gz;
+                    } else {
+                        F0 = a * Gs[sidx];
+                        F1 = a * Gs[NSRC + sidx];
+                        F2 = a * Gs[2 * NSRC + sidx];
+                    }
                     const float *nr = &sm.n[(it + 1) % 3][0][0];  // plane r
                     const int c = (sy + 1) * GX + (sx + 1);
                     n0 = nr[c];
@@ -361,8 +381,28 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
             int32_t base = 0, ax = 0, ay = 0, az = 0;
             if (is_src) {
                 const float rp = mom_cur[0];
-                const float rho = 1.0f + rp;
-                const float inv = recip(rho);
+                float om1 = omega1;
+                if constexpr (VD) {
+                    // rho(phi), omega(phi) and the acceleration that replaces F
+                    const float pc = fminf(fmaxf(phi_to_float(phis), 0.0f), 1.0f);
+                    const float om = recip(fmaf(3.0f, fmaf(ph.dnu, pc, ph.nu_b), 0.5f));
+                    om1 = 1.0f - om;
+                    if (sbnd) {
+                        F0 = F1 = F2 = 0.f;
+                    } else {
+                        const float ir = recip(fmaf(ph.drho, pc, ph.rho_b));
+                        const float cp = (-1.0f / 3.0f) * ph.drho * rp;     // pressure force / G
+                        const float cm = (0.5f * om - 1.0f) * ph.drho;      // viscous force / (Q.G)
+                        const float QG0 = fmaf(mom_cur[4], Gx, fmaf(mom_cur[7], Gy, mom_cur[8] * Gz));
+                        const float QG1 = fmaf(mom_cur[7], Gx, fmaf(mom_cur[5], Gy, mom_cur[9] * Gz));
+                        const float QG2 = fmaf(mom_cur[8], Gx, fmaf(mom_cur[9], Gy, mom_cur[6] * Gz));
+                        F0 = fmaf(fmaf(cm, QG0, fmaf(cp, Gx, F0)), ir, ph.grav[0]);
+                        F1 = fmaf(fmaf(cm, QG1, fmaf(cp, Gy, F1)), ir, ph.grav[1]);
+                        F2 = fmaf(fmaf(cm, QG2, fmaf(cp, Gz, F2)), ir, ph.grav[2]);
+                    }
+                }
+                const float rho = VD ? 1.0f : 1.0f + rp;  // density of the velocity terms
+                const float inv = VD ? 1.0f : recip(rho);
                 const float hF = 0.5f * inv, qF = 0.25f * inv;
                 const float u0 = fmaf(hF, F0, mom_cur[1]), u1 = fmaf(hF, F1, mom_cur[2]), u2 = fmaf(hF, F2, mom_cur[3]);
                 const float Pxx = fmaf(qF * F0, F0, mom_cur[4]), Pyy = fmaf(qF * F1, F1, mom_cur[5]);
@@ -370,8 +410,8 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
                 const float Pxz = fmaf(qF * F0, F2, mom_cur[8]), Pyz = fmaf(qF * F1, F2, mom_cur[9]);
                 // Hermite coefficients, pre-scaled: t(c) = K0 + sum K1 c + ... (see header)
                 const float Jx = fmaf(rho, u0, 0.5f * F0), Jy = fmaf(rho, u1, 0.5f * F1), Jz = fmaf(rho, u2, 0.5f * F2);
-                const float mxx = omega1 * Pxx, myy = omega1 * Pyy, mzz = omega1 * Pzz;
-                const float mxy = omega1 * Pxy, mxz = omega1 * Pxz, myz = omega1 * Pyz;
+                const float mxx = om1 * Pxx, myy = om1 * Pyy, mzz = om1 * Pzz;
+                const float mxy = om1 * Pxy, mxz = om1 * Pxz, myz = om1 * Pyz;
                 const float ru0 = rho * u0, ru1 = rho * u1, ru2 = rho * u2;
                 const float a2xx = fmaf(ru0, u0, mxx) + u0 * F0;
                 const float a2yy = fmaf(ru1, u1, myy) + u1 * F1;
@@ -579,7 +619,7 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
                     const float Hxy = tr3_m0(Xm[5], XB[5], XA[5]);
                     const float drho = m00.m0;
                     const float jx = m10.m0, jy = m01.m0, jz = m00.m1;
-                    const float inv = recip(1.0f + drho);
+                    const float inv = VD ? 1.0f : recip(1.0f + drho);
                     float m[10];
                     m[0] = drho;
                     m[1] = jx * inv;
@@ -643,17 +683,17 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
 }
 
 
-template <int ST, bool PH>
+template <int ST, bool PH, bool VD = false>
 __global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, StateView in, StateView out, int lz,
                                                    int tiles_x, int tiles_y, unsigned long long step_next) {
     __shared__ Smem<PH> sm;
-    step_fused<ST, PH, false, false>(sm, g, ph, sc, in, out, lz, tiles_x, tiles_y, step_next,
-                              xcd_work_item(blockIdx.x, gridDim.x));
+    step_fused<ST, PH, false, false, VD>(sm, g, ph, sc, in, out, lz, tiles_x, tiles_y, step_next,
+                                         xcd_work_item(blockIdx.x, gridDim.x));
 }
 
 // Several lattices in one launch: the work items of domain k are
 // [work_begin, work_begin + tiles * chunks); domains are sorted by work_begin.
-template <int ST, bool PH>
+template <int ST, bool PH, bool VD = false>
 __global__ __launch_bounds__(NT) void k_step_fused_multi(const FusedDomain *__restrict__ doms, int ndom) {
     __shared__ Smem<PH> sm;
     const int w = xcd_work_item(blockIdx.x, gridDim.x);
@@ -685,13 +725,17 @@ __global__ __launch_bounds__(NT) void k_step_fused_multi(const FusedDomain *__re
     ph.noise_key = d.ph.noise_key;
     ph.bc[0] = d.ph.bc[0]; ph.bc[1] = d.ph.bc[1]; ph.bc[2] = d.ph.bc[2];
     ph.bc[3] = d.ph.bc[3]; ph.bc[4] = d.ph.bc[4]; ph.bc[5] = d.ph.bc[5];
+    if constexpr (VD) {
+        ph.rho_b = d.ph.rho_b; ph.drho = d.ph.drho; ph.nu_b = d.ph.nu_b; ph.dnu = d.ph.dnu;
+        ph.grav[0] = d.ph.grav[0]; ph.grav[1] = d.ph.grav[1]; ph.grav[2] = d.ph.grav[2];
+    }
     Scales sc;
     sc.s2 = d.sc.s2; sc.s1 = d.sc.s1; sc.inv_s2 = d.sc.inv_s2; sc.inv_s1 = d.sc.inv_s1;
     StateView in, out;
     in.mom = d.in.mom; in.phi = d.in.phi; out.mom = d.out.mom; out.phi = d.out.phi;
     const int lz = d.lz, tx = d.tiles_x, ty = d.tiles_y, wb = d.work_begin;
     const unsigned long long sn = d.step_next;
-    step_fused<ST, PH, (ST == ST_FP32), true>(sm, g, ph, sc, in, out, lz, tx, ty, sn, w - wb);
+    step_fused<ST, PH, (ST == ST_FP32), true, VD>(sm, g, ph, sc, in, out, lz, tx, ty, sn, w - wb);
 }
 
 }  // namespace fused
@@ -757,18 +801,18 @@ FusedDomain fused_domain(const tslb_ctx *c, StateView in, StateView out, int64_t
 // Launch the fused step over the whole lattice.
 namespace {
 
-template <int ST, bool PH>
+template <int ST, bool PH, bool VD = false>
 void launch_one(unsigned blocks, hipStream_t s, const tslb_ctx *c, StateView in, StateView out, int lz, int tiles_x,
                 int tiles_y, unsigned long long sn) {
     using namespace fused;
-    hipLaunchKernelGGL((k_step_fused<ST, PH>), dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in, out, lz,
-                       tiles_x, tiles_y, sn);
+    hipLaunchKernelGGL((k_step_fused<ST, PH, VD>), dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in, out,
+                       lz, tiles_x, tiles_y, sn);
 }
 
-template <int ST, bool PH>
+template <int ST, bool PH, bool VD = false>
 void launch_multi(unsigned blocks, hipStream_t s, const FusedDomain *doms, int ndom) {
     using namespace fused;
-    hipLaunchKernelGGL((k_step_fused_multi<ST, PH>), dim3(blocks), dim3(NT), 0, s, doms, ndom);
+    hipLaunchKernelGGL((k_step_fused_multi<ST, PH, VD>), dim3(blocks), dim3(NT), 0, s, doms, ndom);
 }
 
 }  // namespace
@@ -780,6 +824,11 @@ hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int
     const int chunks = (c->geo.nz + lz - 1) / lz;
     const unsigned blocks = (unsigned)tiles_x * tiles_y * chunks;
     const unsigned long long sn = (unsigned long long)step_next;
+    if (c->vd) {  // variable density: binary32 storage, two components (validated at creation)
+        if (c->storage != ST_FP32 || !c->phase) return hipErrorInvalidValue;
+        launch_one<ST_FP32, true, true>(blocks, s, c, in, out, lz, tiles_x, tiles_y, sn);
+        return hipGetLastError();
+    }
 #define TSLB_FUSED_CASE(ST)                                                                            \
     case ST:                                                                                           \
         if (c->phase)                                                                                  \
@@ -800,9 +849,14 @@ hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int
 }
 
 hipError_t launch_step_fused_multi(const FusedDomain *doms, int ndom, int total_work, int storage, bool phase,
-                                   hipStream_t s) {
+                                   bool vd, hipStream_t s) {
     if (ndom <= 0 || total_work <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)total_work;
+    if (vd) {
+        if (storage != ST_FP32 || !phase) return hipErrorInvalidValue;
+        launch_multi<ST_FP32, true, true>(blocks, s, doms, ndom);
+        return hipGetLastError();
+    }
 #define TSLB_MULTI_CASE(ST)                                                                            \
     case ST:                                                                                           \
         if (phase)                                                                                     \

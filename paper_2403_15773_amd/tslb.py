@@ -16,7 +16,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtslb.so")
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSTABLE, E_STATE = 0, -1, -2, -3, -4, -5
 BC_PERIODIC, BC_FREESLIP, BC_INLET, BC_OUTFLOW, BC_NOSLIP = 0, 1, 2, 3, 4
@@ -59,6 +59,10 @@ class Params(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("components", ctypes.c_int32),
         ("max_mass_drift", ctypes.c_double),
+        ("variable_density", ctypes.c_int32),
+        ("density_a", ctypes.c_double), ("density_b", ctypes.c_double),
+        ("nu_a", ctypes.c_double), ("nu_b", ctypes.c_double),
+        ("gravity", ctypes.c_double * 3),
     ]
 
 
@@ -129,7 +133,11 @@ def load_library(path: str = LIB_PATH):
 
 def make_params(nx, ny, nz, nu, sigma=0.0, width=3.0, gamma=0.0, eps=-1.0, bc=(0,) * 6, inlet_u=0.0,
                 inlet_d=0.0, inlet_noise=0.0, seed=0, storage="fp32", u_scale=0.0, check_interval=0, device=0,
-                device_buffer=None, device_buffer_bytes=0, stream=None, components=2, max_mass_drift=0.0) -> Params:
+                device_buffer=None, device_buffer_bytes=0, stream=None, components=2, max_mass_drift=0.0,
+                density_a=None, density_b=None, nu_a=None, nu_b=None, gravity=(0.0, 0.0, 0.0)) -> Params:
+    """Lattice parameters.  density_a/density_b/nu_a/nu_b given select the
+    variable-density step (then rho_dev of the state is the normalised pressure
+    p* and nu is unused)."""
     lib = load_library()
     p = Params()
     lib.tslb_params_init(ctypes.byref(p))
@@ -148,6 +156,12 @@ def make_params(nx, ny, nz, nu, sigma=0.0, width=3.0, gamma=0.0, eps=-1.0, bc=(0
     p.stream = stream
     p.components = int(components)
     p.max_mass_drift = float(max_mass_drift)
+    if density_a is not None:
+        p.variable_density = 1
+        p.density_a, p.density_b = float(density_a), float(density_b)
+        p.nu_a, p.nu_b = float(nu_a), float(nu_b)
+    for c in range(3):
+        p.gravity[c] = float(gravity[c])
     return p
 
 

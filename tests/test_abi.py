@@ -77,6 +77,35 @@ def test_invalid_parameters_rejected_on_host(lib, field, value):
     assert len(lib.tslb_last_error(None)) > 0
 
 
+def _vd_params(lib, **over):
+    p = tslb.Params()
+    lib.tslb_params_init(ctypes.byref(p))
+    p.variable_density, p.density_a, p.density_b, p.nu_a, p.nu_b = 1, 10.0, 1.0, 0.05, 0.02
+    for k, v in over.items():
+        if k == "gravity":
+            for c in range(3):
+                p.gravity[c] = v[c]
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def test_variable_density_parameters(lib):
+    assert lib.tslb_required_bytes(ctypes.byref(_vd_params(lib))) == 2 * 11 * 4 * 32 ** 3
+    assert lib.tslb_required_bytes(ctypes.byref(_vd_params(lib, gravity=(0.0, 0.0, -1e-5)))) > 0
+    bad = [dict(density_a=0.0), dict(density_b=-1.0), dict(nu_a=0.0), dict(nu_b=-1.0), dict(components=1),
+           dict(storage=tslb.STORE_FP16), dict(variable_density=2), dict(gravity=(float("nan"), 0.0, 0.0)),
+           dict(density_a=float("inf"))]
+    for over in bad:
+        p = _vd_params(lib, **over)
+        assert lib.tslb_required_bytes(ctypes.byref(p)) == 0, over
+        h = ctypes.c_void_p()
+        assert lib.tslb_create(ctypes.byref(p), ctypes.byref(h)) == tslb.E_INVAL, over
+    # gravity belongs to the variable-density step
+    p = _vd_params(lib, variable_density=0, gravity=(0.0, 1e-6, 0.0))
+    assert lib.tslb_required_bytes(ctypes.byref(p)) == 0
+
+
 @pytest.mark.parametrize("bc", [(1, 0, 0, 0, 0, 0), (2, 1, 0, 0, 0, 0), (0, 0, 0, 0, 1, 2), (9, 9, 0, 0, 0, 0)])
 def test_invalid_boundary_sets_rejected(lib, bc):
     p = tslb.Params()

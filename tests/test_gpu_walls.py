@@ -1,7 +1,8 @@
 """The walled-step flows that pin the oracle (tests/test_oracle_walls.py), run
-on the HIP path: the no-slip and free-slip channel shear modes and the uniform
-stream through inlet, outflow and free-slip faces, against the oracle node by
-node (1e-5 per-field relative L-infinity) and against the closed forms."""
+on the HIP path: the no-slip and free-slip channel shear modes (against the
+oracle node by node after 200 steps, 1e-5 relative L-infinity of the velocity
+and of the shear stress, and their decay rate against the closed form over 650
+steps) and the uniform stream through inlet, outflow and free-slip faces."""
 import numpy as np
 import pytest
 
@@ -28,7 +29,7 @@ def _mode_state(n, wall_axis, comp, rule, omega):
         H, s0, mode, dmode = n - 1, 0.0, np.sin, np.cos
     else:
         H, s0, mode, dmode = n - 2, 0.5, np.cos, lambda v: -np.sin(v)
-    k, A = np.pi / H, 1e-4
+    k, A = np.pi / H, 1e-3
     st["u"][comp] = A * mode(k * (s - s0))
     st["P"][P_INDEX[tuple(sorted((wall_axis, comp)))]] = -(CS2 / omega) * A * k * dmode(k * (s - s0))
     bc = [0] * 6
@@ -52,19 +53,17 @@ def test_channel_shear_mode_against_oracle_and_closed_form(rule, n, wall_axis, c
     o.set_physical(rho=np.ones((nz, ny, nx)), u=f32["u"].astype(np.float64), P=f32["P"].astype(np.float64),
                    phi=f32["phi"].astype(np.float64))
     mean_axes = tuple(a for a in range(3) if a != 2 - wall_axis)
-    ts, amps = [], []
-    sim.step(50)
-    o.step(50)
-    for _ in range(12):
-        g = sim.physical()
-        u = g["u"][comp].astype(np.float64).mean(axis=mean_axes)
-        ts.append(sim.step_index)
-        amps.append((u * basis).sum() / (basis ** 2).sum())
-        sim.step(50)
-        o.step(50)
+    sim.step(200)
+    o.step(200)
     g = sim.physical()
     r = o.physical()
     o.close()
+    ts, amps = [], []
+    for _ in range(10):
+        sim.step(50)
+        u = sim.physical()["u"][comp].astype(np.float64).mean(axis=mean_axes)
+        ts.append(sim.step_index)
+        amps.append((u * basis).sum() / (basis ** 2).sum())
     sim.close()
     for name, a, b in [("u", g["u"][comp], r["u"][comp]), ("P", g["P"][P_INDEX[tuple(sorted((wall_axis, comp)))]],
                                                             r["P"][P_INDEX[tuple(sorted((wall_axis, comp)))]]),
