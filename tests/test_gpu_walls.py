@@ -65,16 +65,16 @@ def test_channel_shear_mode_against_oracle_and_closed_form(rule, n, wall_axis, c
         ts.append(sim.step_index)
         amps.append((u * basis).sum() / (basis ** 2).sum())
     sim.close()
-    for name, a, b in [("u", g["u"][comp], r["u"][comp]), ("P", g["P"][P_INDEX[tuple(sorted((wall_axis, comp)))]],
-                                                            r["P"][P_INDEX[tuple(sorted((wall_axis, comp)))]]),
-                       ("rho-1", g["rho_dev"], r["rho"] - 1.0)]:
-        scale = max(np.abs(b).max(), 1e-300)
+    # the velocity against its own scale; the shear stress (nu k u, about 1 % of u here, below the
+    # rounding of the populations that carry u) against the velocity scale; rho - 1 (rounding level
+    # in this incompressible mode) by an absolute bound
+    su = np.abs(r["u"][comp]).max()
+    sP = P_INDEX[tuple(sorted((wall_axis, comp)))]
+    for name, a, b, scale in [("u", g["u"][comp], r["u"][comp], su), ("P", g["P"][sP], r["P"][sP], su)]:
         err = np.abs(np.asarray(a, np.float64) - b).max() / scale
-        _say("  %s: %.2e (scale %.2e)" % (name, err, scale))
-        if name != "rho-1":
-            assert err <= 1e-5, name
-        else:  # rho - 1 is at rounding level here: absolute bound
-            assert np.abs(np.asarray(a, np.float64) - b).max() <= 1e-9
+        _say("  %s: %.2e (scale %.2e, own max %.2e)" % (name, err, scale, np.abs(b).max()))
+        assert err <= 1e-5, name
+    assert np.abs(g["rho_dev"].astype(np.float64) - (r["rho"] - 1.0)).max() <= 1e-9
     rate = -np.polyfit(ts, np.log(amps), 1)[0]
     ratio = rate / (k ** 2 * CS2 * (1 / omega - 0.5))
     if rule == 4:
