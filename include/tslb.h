@@ -229,6 +229,32 @@ int tslb_set_state_raw(tslb_ctx *ctx, const void *host, size_t bytes, int64_t st
  * first.  Synchronises.  TSLB_E_STATE before any state was set. */
 int tslb_diagnostics(tslb_ctx *ctx, double *mass, double *phase_sum, int64_t *step, int32_t *finite);
 
+/* For callers that cannot allocate device memory (work under HIP stream
+ * capture, serving loops and harnesses that forbid hipMalloc): the
+ * diagnostics of tslb_diagnostics for one state buffer the caller holds in
+ * device memory, computed with no allocation of any kind.
+ *   p      parameters of the lattice the buffer belongs to (validated as by
+ *          tslb_create; device_buffer and stream are ignored, p->device is
+ *          made current);
+ *   state  device pointer, read only, 4-byte aligned: one state buffer in the
+ *          layout tslb_get_state_raw() returns (tslb_state_bytes() bytes);
+ *          every node is summed as stored (tslb_diagnostics fills the
+ *          boundary layers first; a buffer written by a step or read back by
+ *          tslb_get_state_raw already has them);
+ *   stream hipStream_t the two kernels are queued on (NULL: the null stream);
+ *   out    device pointer, 8-byte aligned, receives 3 doubles: the mass, the
+ *          phase sum and 1.0 if every stored moment is finite (else 0.0),
+ *          bit for bit what tslb_diagnostics returns for the same buffer.
+ * Asynchronous: out is valid once the stream has reached it.  The partial sums
+ * live in a static device array (24.6 KB per device, held until the process
+ * ends) with room for 1024 blocks; the kernels stride over the nodes, so every
+ * lattice tslb_create accepts fits, and parameters it rejects are rejected
+ * here (TSLB_E_INVAL).  Calls on one device share that array: calls that
+ * overlap in time (other streams or host threads) race and must be
+ * serialised by the caller.  TSLB_E_DEVICE for a failed launch; the message
+ * is in tslb_last_error(NULL). */
+int tslb_diagnostics_noalloc(const tslb_params *p, const void *state, void *stream, double *out);
+
 /* Current step index (no synchronisation). */
 int64_t tslb_step_index(const tslb_ctx *ctx);
 

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtslb.so")
-SOURCES = ["tslb_api.hip", "tslb_kernels.hip", "tslb_step_fused.hip", "tslb_group.hip", "tslb_probe.hip"]
+SOURCES = ["tslb_api.hip", "tslb_kernels.hip", "tslb_step_fused.hip", "tslb_group.hip", "tslb_probe.hip",
+           "tslb_noalloc.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -31,6 +31,7 @@ EXPORTS = [
     "tslb_group_create", "tslb_group_admit", "tslb_group_poll", "tslb_group_status", "tslb_group_destroy",
     "tslb_group_last_error", "tslb_stats_start", "tslb_stats_stop", "tslb_stats_get", "tslb_probe_projection",
     "tslb_set_state_rest", "tslb_step_kernel_times", "tslb_device_memory", "tslb_group_busy", "tslb_device_bytes",
+    "tslb_diagnostics_noalloc",
 ]
 KERNEL_FUSED, KERNEL_GATHER = 0, 1
 
@@ -98,6 +99,7 @@ def load_library(path: str = LIB_PATH):
             "tslb_set_state_raw": (ctypes.c_int, [vp, vp, ctypes.c_size_t, ctypes.c_int64]),
             "tslb_diagnostics": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
+            "tslb_diagnostics_noalloc": (ctypes.c_int, [P, vp, vp, vp]),
             "tslb_step_index": (ctypes.c_int64, [vp]),
             "tslb_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
             "tslb_last_step_kernel_ms": (ctypes.c_double, [vp]),
@@ -201,6 +203,16 @@ def projection_probe(kind, coef, reps: int, iters: int = 10, device: int = 0, wa
     if rc != OK:
         raise TslbError(rc, lib.tslb_last_error(None).decode())
     return m.value, out
+
+
+def diagnostics_noalloc(params: Params, state_ptr: int, stream_ptr, out_ptr: int) -> None:
+    """Queue tslb_diagnostics_noalloc: state_ptr and out_ptr are device
+    addresses (one state buffer; three doubles), stream_ptr a hipStream_t or
+    None.  Nothing is allocated."""
+    lib = load_library()
+    rc = lib.tslb_diagnostics_noalloc(ctypes.byref(params), state_ptr, stream_ptr, out_ptr)
+    if rc != OK:
+        raise TslbError(rc, lib.tslb_last_error(None).decode())
 
 
 def required_bytes(params: Params) -> int:

@@ -90,6 +90,23 @@ def _vd_params(lib, **over):
     return p
 
 
+def test_noalloc_diagnostics_rejects_bad_arguments_on_host(lib):
+    """The allocation-free diagnostics entry point checks its arguments before
+    any device call."""
+    p = tslb.Params()
+    lib.tslb_params_init(ctypes.byref(p))
+    assert lib.tslb_diagnostics_noalloc(None, 256, None, 256) == tslb.E_INVAL
+    assert lib.tslb_diagnostics_noalloc(ctypes.byref(p), None, None, 256) == tslb.E_INVAL
+    assert lib.tslb_diagnostics_noalloc(ctypes.byref(p), 256, None, None) == tslb.E_INVAL
+    assert lib.tslb_diagnostics_noalloc(ctypes.byref(p), 258, None, 256) == tslb.E_INVAL  # state not 4-byte aligned
+    assert lib.tslb_diagnostics_noalloc(ctypes.byref(p), 256, None, 260) == tslb.E_INVAL  # out not 8-byte aligned
+    p.nu = -1.0
+    assert lib.tslb_diagnostics_noalloc(ctypes.byref(p), 256, None, 256) == tslb.E_INVAL
+    p.nu, p.device = 0.1, 4096
+    assert lib.tslb_diagnostics_noalloc(ctypes.byref(p), 256, None, 256) == tslb.E_INVAL
+    assert len(lib.tslb_last_error(None)) > 0
+
+
 def test_variable_density_parameters(lib):
     assert lib.tslb_required_bytes(ctypes.byref(_vd_params(lib))) == 2 * 11 * 4 * 32 ** 3
     assert lib.tslb_required_bytes(ctypes.byref(_vd_params(lib, gravity=(0.0, 0.0, -1e-5)))) > 0
