@@ -51,12 +51,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="jet512", choices=["jet128", "jet512", "droplet32", "tgv256"])
+    ap.add_argument("--workload", default="jet512", choices=["jet128", "jet512", "droplet32", "tgv256", "jet128vd"])
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16", "fp16q"])
     ap.add_argument("--variants", default="fp16,bf16,fp16q", help="other storage types timed on the same workload")
     ap.add_argument("--secondary", default="jet128", help="another workload timed in binary32 ('' = skip)")
     ap.add_argument("--serve", type=int, default=256, help="requests in the serving stream (0 = skip)")
     ap.add_argument("--single", type=int, default=1, help="also time the one-component Taylor-Green vortex (0 = skip)")
+    ap.add_argument("--vd", type=int, default=1, help="also time the variable-density 128x128x512 jet (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-oracle sample budget (0 = skip)")
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the copy-kernel ceiling probe (0 = skip)")
     ap.add_argument("--kernel", default="fused", choices=["fused", "gather"])
@@ -83,6 +84,11 @@ def workload_state(name):
 def describe(name, p):
     if name.startswith("tgv"):
         return {"workload": "Taylor-Green vortex %d^3, one component, U0=0.05, Re=1600, periodic" % p["nx"],
+                "nodes": p["nx"] * p["ny"] * p["nz"]}
+    if name == "jet128vd":
+        return {"workload": "round jet %dx%dx%d, D=%g, U=%g, jet/ambient density %g/%g, nu %g, We=%g, variable-density "
+                            "step" % (p["nx"], p["ny"], p["nz"], p["inlet_d"], p["inlet_u"], p["density_a"],
+                                      p["density_b"], p["nu_a"], round(p["inlet_u"] ** 2 * p["inlet_d"] / p["sigma"])),
                 "nodes": p["nx"] * p["ny"] * p["nz"]}
     if name.startswith("jet"):
         d, u = p["inlet_d"], p["inlet_u"]
@@ -207,7 +213,8 @@ def cpu_baseline(name, p, st, budget_s):
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
     o = Oracle(p["nx"], p["ny"], p["nz"], nu=p["nu"], sigma=p["sigma"], width=p["width"], eps=1e-4, bc=p["bc"],
                inlet_u=p.get("inlet_u", 0.0), inlet_d=p.get("inlet_d", 0.0), inlet_noise=p.get("inlet_noise", 0.0),
-               seed=p.get("seed", 0))
+               seed=p.get("seed", 0), rho_a=p.get("density_a"), rho_b=p.get("density_b"), nu_a=p.get("nu_a"),
+               nu_b=p.get("nu_b"))
     if st is None:
         from paper_2403_15773_amd import inputs
         st = inputs.quiescent(p["nx"], p["ny"], p["nz"])
@@ -305,6 +312,12 @@ def main():
                   "roofline_frac": r["achieved"] / HBM_PEAK_GBS if r["achieved"] else None,
                   "frac_of_copy_ceiling": r["achieved"] / copy["gbps"] if (copy and r["achieved"]) else None,
                   "finite": r["finite"]}
+    vd = None
+    if a.vd and a.workload != "jet128vd":
+        r = run_lattice("jet128vd", "fp32", a.steps, a.warmup, a.kernel)
+        vd = describe("jet128vd", r["p"]) | {
+            "value": r["glups"], "unit": "GLUPS", "kernel_ms": r["kernel_ms"], "bytes_per_node": r["bpn"],
+            "roofline_frac": r["achieved"] / HBM_PEAK_GBS if r["achieved"] else None, "finite": r["finite"]}
     rec = {
         "metric": "GLUPS (lattice-node updates per second / 1e9) and fraction of the HBM roofline",
         "value": m["glups"],
@@ -330,6 +343,7 @@ def main():
         "storage_variants": variants,
         "secondary": secondary,
         "single_component": single,
+        "variable_density": vd,
         "projection_probe": projection_probe(1 << 22, 64) if a.probe else None,
         "serving": serving(a.serve) if a.serve > 0 else None,
         "cpu_baseline": cpu_baseline(a.workload, p, m["st"], a.cpu_seconds),

@@ -356,6 +356,30 @@ def test_full_jet_step_matches_oracle_at_every_node():
     assert_parity(g1, r1, TOL_FP32, "full-jet one step")
 
 
+def test_full_jet_200_steps_from_rest_matches_oracle_at_every_node():
+    """The 128 x 128 x 512 jet (D = 20, Re = 5000, We = 100) in the launch
+    configuration the benchmark times, 200 steps from rest on the GPU and on the
+    FP64 oracle (4.6 GB of populations, about 80 s on the host's cores): every
+    node of every field within 1e-5."""
+    from oracle import Oracle
+    from paper_2403_15773_amd.tslb import Simulation
+    _say("full jet 128x128x512: 200 steps from rest, GPU vs oracle at every node")
+    p = inputs.WORKLOADS["jet128"]["params"]
+    with Simulation(**p, eps=EPS) as s:
+        s.set_state_rest(step=0)
+        s.step(200)
+        g = s.physical()
+    assert g["u"][2].max() > 0.04 and g["phi"].max() > 0.9  # the jet has entered
+    o = Oracle(p["nx"], p["ny"], p["nz"], nu=p["nu"], sigma=p["sigma"], width=p["width"], eps=EPS, bc=p["bc"],
+               inlet_u=p["inlet_u"], inlet_d=p["inlet_d"], inlet_noise=p["inlet_noise"], seed=p["seed"])
+    st = inputs.quiescent(p["nx"], p["ny"], p["nz"])
+    o.set_physical(**st, step=0)
+    o.step(200)
+    r = o.physical()
+    o.close()
+    assert_parity(g, r, TOL_FP32, "full jet 200 steps")
+
+
 def _hydro_parity(p, state, steps, label, step0=0):
     """One-component GPU path against the oracle with sigma = 0: the phase field
     then leaves the hydrodynamics alone (F = 0), so rho, u and P must agree."""
