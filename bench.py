@@ -51,7 +51,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="jet512", choices=["jet128", "jet512", "droplet32", "tgv256", "jet128vd"])
+    ap.add_argument("--workload", default="jet512",
+                    choices=["jet128", "jet512", "jet400", "droplet32", "tgv256", "jet128vd"])
+    ap.add_argument("--paper-domain", type=int, default=1,
+                    help="also time the paper's 400x400x800 jet domain, for context beside its GLUPS (0 = skip)")
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16", "fp16q"])
     ap.add_argument("--variants", default="fp16,bf16,fp16q", help="other storage types timed on the same workload")
     ap.add_argument("--secondary", default="jet128", help="another workload timed in binary32 ('' = skip)")
@@ -312,6 +315,15 @@ def main():
                   "roofline_frac": r["achieved"] / HBM_PEAK_GBS if r["achieved"] else None,
                   "frac_of_copy_ceiling": r["achieved"] / copy["gbps"] if (copy and r["achieved"]) else None,
                   "finite": r["finite"]}
+    paper = None
+    if a.paper_domain and a.workload != "jet400":
+        r = run_lattice("jet400", "fp32", a.steps, a.warmup, a.kernel)
+        paper = describe("jet400", r["p"]) | {
+            "value": r["glups"], "unit": "GLUPS", "kernel_ms": r["kernel_ms"], "bytes_per_node": r["bpn"],
+            "roofline_frac": r["achieved"] / HBM_PEAK_GBS if r["achieved"] else None, "finite": r["finite"],
+            "paper_glups_other_hardware": {"RTX 3090": 1.5, "A100": 2.0},
+            "note": "the paper's own jet domain (128 million nodes) and its quoted GLUPS on other hardware and "
+                    "code: context, not a baseline of this metric"}
     vd = None
     if a.vd and a.workload != "jet128vd":
         r = run_lattice("jet128vd", "fp32", a.steps, a.warmup, a.kernel)
@@ -344,6 +356,7 @@ def main():
         "secondary": secondary,
         "single_component": single,
         "variable_density": vd,
+        "paper_domain": paper,
         "projection_probe": projection_probe(1 << 22, 64) if a.probe else None,
         "serving": serving(a.serve) if a.serve > 0 else None,
         "cpu_baseline": cpu_baseline(a.workload, p, m["st"], a.cpu_seconds),

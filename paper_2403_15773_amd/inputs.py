@@ -125,6 +125,10 @@ WORKLOADS = {
     # 512x512x2048 round jet, D = 40, U = 0.05, Re = 5000, We = 2000, 200 warm-up + 500 timed
     "jet512": dict(params=jet_params(512, 512, 2048, d=40, u=0.05, re=5000, we=2000, seed=3), steps=500,
                    init="quiescent"),
+    # the paper's own jet domain (Results, Table 1; Performances: 128 million nodes): 400x400x800,
+    # D = 40 (10 D x 10 D x 20 D), U = 0.05, Re = 5000, We = 2000
+    "jet400": dict(params=jet_params(400, 400, 800, d=40, u=0.05, re=5000, we=2000, seed=4), steps=500,
+                   init="quiescent"),
     # the 128x128x512 jet with components of different density: the injected component ten times
     # denser than the ambient, equal viscosities (Re = 5000 in the jet), We = 100
     "jet128vd": dict(params=jet_params(128, 128, 512, d=20, u=0.05, re=5000, we=100, seed=2)
