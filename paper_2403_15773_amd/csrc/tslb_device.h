@@ -158,21 +158,29 @@ __device__ __forceinline__ float decode_moment(uint32_t b, int p, const Scales &
     }
 }
 
+// Stores of a new state carry the non-temporal hint: the fused step never reads
+// back what it writes, and lines written without the hint take L2 capacity from
+// the halo lines that its neighbouring workgroups read again.
+template <class T, class P>
+__device__ __forceinline__ void store_nt(P ptr, T v) {
+    __builtin_nontemporal_store(v, ptr);
+}
+
 template <int ST, bool G = false>
 __device__ __forceinline__ void store_moment(void *mom, long long ld, int p, long long id, float v, const Scales &sc) {
     if constexpr (ST == ST_FP32) {
-        mem<G>((float *)mom)[p * ld + id] = v;
+        store_nt(&mem<G>((float *)mom)[p * ld + id], v);
     } else if constexpr (ST == ST_FP16Q) {
         if (p < 4)
-            mem<G>((float *)mom)[p * ld + id] = v;
+            store_nt(&mem<G>((float *)mom)[p * ld + id], v);
         else
-            mem<G>((_Float16 *)((float *)mom + 4 * ld) + (p - 4) * ld)[id] = (_Float16)(v * sc.inv_s2);
+            store_nt(&mem<G>((_Float16 *)((float *)mom + 4 * ld) + (p - 4) * ld)[id], (_Float16)(v * sc.inv_s2));
     } else if constexpr (ST == ST_FP16) {
-        mem<G>((_Float16 *)mom + p * ld)[id] = (_Float16)(v * ((p >= 1 && p < 4) ? sc.inv_s1 : sc.inv_s2));
+        store_nt(&mem<G>((_Float16 *)mom + p * ld)[id], (_Float16)(v * ((p >= 1 && p < 4) ? sc.inv_s1 : sc.inv_s2)));
     } else {
         const uint32_t b = __float_as_uint(v * ((p >= 1 && p < 4) ? sc.inv_s1 : sc.inv_s2));
         const uint32_t r = ((b & 0x7fffffffu) > 0x7f800000u) ? (b | 0x00400000u) : (b + 0x7fffu + ((b >> 16) & 1u));
-        mem<G>((uint16_t *)mom + p * ld)[id] = (uint16_t)(r >> 16);
+        store_nt(&mem<G>((uint16_t *)mom + p * ld)[id], (uint16_t)(r >> 16));
     }
 }
 

@@ -646,7 +646,7 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
                         const long long ib = (long long)gxs + (long long)g.nx * gys + plane * zb;
 #pragma unroll
                         for (int k = 0; k < 10; ++k) store_moment<ST, G>(out.mom, g.ld, k, ib, mb[k], sc);
-                        if constexpr (PH) mem<G>(out.phi)[ib] = pb;
+                        if constexpr (PH) store_nt(&mem<G>(out.phi)[ib], pb);
                     }
                     // the node itself: interior, or on an x/y wall (face rule of step t+1)
                     int32_t po = phin;
@@ -657,7 +657,7 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
                     const long long id = (long long)gxs + (long long)g.nx * gys + plane * zd;
 #pragma unroll
                     for (int k = 0; k < 10; ++k) store_moment<ST, G>(out.mom, g.ld, k, id, m[k], sc);
-                    if constexpr (PH) mem<G>(out.phi)[id] = po;
+                    if constexpr (PH) store_nt(&mem<G>(out.phi)[id], po);
                 }
                 // carry: plane r gets X(+1) = XC, X(0) = X0; plane r+1 gets X(+1) = Xp
 #pragma unroll
