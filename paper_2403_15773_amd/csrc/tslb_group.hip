@@ -9,6 +9,7 @@
 // kRing launches are in flight, and a slot's pinned host copy is rewritten only
 // after the event of the launch that last used it has completed.
 #include <algorithm>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -42,6 +43,11 @@ struct tslb_group {
     int64_t completed = -1;      // every launch <= completed has finished
     hipEvent_t admit_ev = nullptr;
     std::string err;
+    // chunk bound of each launch class (storage type x component count, and the
+    // variable-density step), kept while the class's stepping members stay the same
+    static constexpr int kPlanClasses = 2 * 4 + 1;
+    std::vector<const tslb_ctx *> plan_members[kPlanClasses];
+    int plan_bound[kPlanClasses] = {};
 };
 
 namespace {
@@ -51,6 +57,7 @@ constexpr int kStorageTypes = 4;  // TSLB_STORE_FP32 .. TSLB_STORE_FP16Q
 // step (binary32, two components) as a class of its own
 constexpr int kClasses = 2 * kStorageTypes + 1;
 constexpr int kClassVD = 2 * kStorageTypes;
+static_assert(kClasses == tslb_group::kPlanClasses, "one chunk plan per launch class");
 int class_of(const tslb_ctx *c) { return c->vd ? kClassVD : 2 * c->storage + (c->phase ? 1 : 0); }
 
 int gfail(tslb_group *g, int code, const std::string &msg) {
@@ -85,6 +92,80 @@ int refresh_completed(tslb_group *g) {
     return TSLB_OK;
 }
 
+// z chunk length of a lattice of nz planes under the bound L: ceil(nz / L)
+// chunks of near-equal length.
+int chunk_under_bound(int nz, int L) {
+    const int k = (nz + L - 1) / L;
+    return (nz + k - 1) / k;
+}
+
+// End time, in pipeline planes, of one launch whose work items take cost[i]
+// planes each: the items are split into eight contiguous ranges, one per XCD
+// (xcd_work_item), and the compute units of an XCD take their range's items
+// in order as they free up.
+long long launch_end(const std::vector<int> &cost, int cus, std::vector<long long> &heap) {
+    const int n = (int)cost.size(), per_xcd = std::max(1, cus / 8);
+    const int q8 = n >> 3, rem8 = n & 7;
+    long long end = 0;
+    int begin = 0;
+    for (int x = 0; x < 8; ++x) {
+        const int cnt = q8 + (x < rem8 ? 1 : 0);
+        heap.assign((size_t)std::min(per_xcd, std::max(cnt, 1)), 0);  // free times, a min-heap
+        for (int i = begin; i < begin + cnt; ++i) {
+            std::pop_heap(heap.begin(), heap.end(), std::greater<long long>());
+            heap.back() += cost[(size_t)i];
+            std::push_heap(heap.begin(), heap.end(), std::greater<long long>());
+        }
+        for (long long t : heap) end = std::max(end, t);
+        begin += cnt;
+    }
+    return end;
+}
+
+// The chunk bound of launch class cl: every stepping member of the class
+// splits its z extent into chunks under one bound L, and the launch takes the
+// L whose simulated end time is earliest (a workgroup on a chunk of l planes
+// walks l + 6 pipeline planes, so long chunks recompute less, short ones leave
+// fewer compute units idle while the last items finish).  The choice is kept
+// until a member is admitted or leaves, or one of the class stops stepping.
+// The result of a step does not depend on the chunk length.
+int plan_chunk_bound(tslb_group *g, int cl) {
+    std::vector<const tslb_ctx *> now;
+    int cus = 0;
+    for (const tslb_group::Member &m : g->members)
+        if (m.remaining > 0 && class_of(m.ctx) == cl) {
+            now.push_back(m.ctx);
+            cus = std::max(cus, m.ctx->cu_count);
+        }
+    if (now.empty()) return 64;
+    if (now == g->plan_members[cl] && g->plan_bound[cl] > 0) return g->plan_bound[cl];
+    static const int kBounds[] = {8, 12, 16, 24, 32, 48, 64, 96, 128};
+    std::vector<int> cost;
+    std::vector<long long> heap;
+    long long best = -1;
+    int best_L = 64;
+    for (int L : kBounds) {
+        cost.clear();
+        for (const tslb_ctx *c : now) {
+            const int nz = c->geo.nz, lz = chunk_under_bound(nz, L);
+            const int chunks = (nz + lz - 1) / lz;
+            const int tiles = fused_work_items(c, nz);  // one chunk of nz planes: the tile count
+            for (int j = 0; j < chunks; ++j) {
+                const int planes = std::min(lz, nz - j * lz) + 6;
+                for (int t = 0; t < tiles; ++t) cost.push_back(planes);
+            }
+        }
+        const long long e = launch_end(cost, std::max(cus, 8), heap);
+        if (best < 0 || e <= best) {  // ties go to the longer chunks
+            best = e;
+            best_L = L;
+        }
+    }
+    g->plan_members[cl] = now;
+    g->plan_bound[cl] = best_L;
+    return best_L;
+}
+
 void release_all(tslb_group *g) {
     for (int s = 0; s < tslb_group::kRing; ++s) {
         if (g->ev[s]) (void)hipEventDestroy(g->ev[s]);
@@ -111,6 +192,7 @@ void group_detach(tslb_group *g, tslb_ctx *c) {
             g->members.erase(g->members.begin() + (long)i);
             break;
         }
+    for (int &b : g->plan_bound) b = 0;  // a later context may reuse c's address
     c->group = nullptr;
 }
 
@@ -181,6 +263,7 @@ int tslb_group_admit(tslb_group *g, tslb_ctx *c, int64_t nsteps) {
     // a member with no steps is done once the work queued so far has finished
     g->members.push_back({c, nsteps, nsteps > 0 ? -1 : g->launches - 1, bytes});  // reserved: no throw
     g->bytes_in_use += bytes;
+    for (int &b : g->plan_bound) b = 0;
     c->group = g;
     return TSLB_OK;
 }
@@ -221,29 +304,18 @@ int tslb_group_poll(tslb_group *g, tslb_ctx **done, int32_t cap, int32_t *ndone)
         rc = refresh_completed(g);
         if (rc) return rc;
     }
-    // z chunks: a lattice alone takes short chunks to fill the device; in a
-    // batch the others fill it, so every member takes long chunks (less halo
-    // recomputed) once the batch has a workgroup per compute unit that way.
-    // The result does not depend on the chunk length.
-    long long long_work = 0;
-    int cus = 0;
-    for (const tslb_group::Member &m : g->members) {
-        if (m.remaining <= 0) continue;
-        long_work += fused_work_items(m.ctx, std::min(64, m.ctx->geo.nz));
-        cus = std::max(cus, m.ctx->cu_count);
-    }
-    const bool long_chunks = long_work >= cus;
     FusedDomain *h = g->h_tab[slot];
     int nrec = 0;
     // one launch per class (storage type, component count) present
     int first[kClasses] = {}, count[kClasses] = {}, work[kClasses] = {};
     for (int cl = 0; cl < kClasses; ++cl) {
         first[cl] = nrec;
+        const int bound = plan_chunk_bound(g, cl);
         for (tslb_group::Member &m : g->members) {
             tslb_ctx *c = m.ctx;
             if (m.remaining <= 0 || class_of(c) != cl) continue;
             h[nrec] = fused_domain(c, c->buf[c->cur], c->buf[c->cur ^ 1], c->step + 1, work[cl],
-                                   long_chunks ? std::min(64, c->geo.nz) : 0);
+                                   chunk_under_bound(c->geo.nz, bound));
             work[cl] += h[nrec].work_count;
             ++nrec;
             ++count[cl];
