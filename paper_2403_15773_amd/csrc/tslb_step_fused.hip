@@ -303,11 +303,9 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
 #pragma unroll
         for (int k = 0; k < 10; ++k) mom_cur[k] = decode_moment<ST>(mom[k], k, sc);
         if (is_src && it >= 3) load_moments(r + 1, mom);
-        // phase plane p + 2, staged at the end of this iteration.  Issued here, next
-        // to the moment prefetch: at the loop latch the compiler waits for the
-        // moment words with a count that covers every memory operation issued so
-        // far (loads and stores share one counter), so a load issued late in the
-        // iteration would be waited for in full there.
+        // phase plane p + 2, staged at the start of phase B.  Issued here, next to
+        // the moment prefetch, so that both have all of phase A to arrive (both are
+        // waited for at the start of phase B).
         if constexpr (PH) {
             if (it + 3 <= nit) load_phi(p + 2, phi_next);
         }
@@ -572,6 +570,25 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
         __syncthreads();
 
         // ================= phase B =================
+        // Wait here, before any store of the iteration, for the loads issued at its
+        // top (vmcnt 0; expcnt and lgkmcnt fields at their maxima, i.e. not waited
+        // for).  Loads and stores share one in-order counter, and the stores below
+        // are conditional, so a wait for the prefetched words placed after them (at
+        // the phase staging or at the loop latch, where the prefetched moments are
+        // copied) can only be vmcnt(0) and also waits until every store of the
+        // iteration has been acknowledged.  Waited for here, on every path, the
+        // loads are known complete at the latch and the stores drain during the
+        // next iteration.
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        // ---- S1: stage phi(p + 2) for the geometry of the next iteration (slot of
+        // plane p - 2, whose last reader, the sources of phase A, is done) ----
+        if constexpr (PH) {
+            if (it + 3 <= nit) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+                    if (phi_item[k] >= 0) sm.phi[(it + 2) & 3][phi_item[k]] = phi_next[k];
+            }
+        }
         if (it >= 4) {
             // ---- S5b/S6: gather at the destination and finish plane r - 1 ----
             if (is_dst) {
@@ -668,14 +685,6 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
                 }
                 PA = PC + prest + pin;
                 PC = pup;
-            }
-        }
-        // ---- S1: stage phi(p + 2) for the geometry of the next iteration ----
-        if constexpr (PH) {
-            if (it + 3 <= nit) {
-    #pragma unroll
-                for (int k = 0; k < 2; ++k)
-                    if (phi_item[k] >= 0) sm.phi[(it + 2) & 3][phi_item[k]] = phi_next[k];
             }
         }
         __syncthreads();
