@@ -437,26 +437,6 @@ def test_single_component_jet_parity():
     _hydro_parity(p, inputs.quiescent(24, 24, 40), 200, "single-component jet", step0=5)
 
 
-def _pattern_state(nx, ny, nz):
-    """A smooth synthetic state on the whole lattice (binary32, separable products of
-    sines): phi in [0.1, 0.9] with interfaces about 10 nodes wide, |u| <= 0.02,
-    rho - 1 ~ 1e-3, P ~ 1e-4; cheap to generate for 5e8 nodes."""
-    x, y, z = (np.arange(n, dtype=np.float32) for n in (nx, ny, nz))
-    s = lambda v, L, ph=0.0: np.sin(np.float32(2 * np.pi / L) * v + np.float32(ph)).astype(np.float32)  # noqa: E731
-    sh = (nz, ny, nx)
-    st = {"rho_dev": np.empty(sh, np.float32), "u": np.empty((3,) + sh, np.float32),
-          "P": np.empty((6,) + sh, np.float32), "phi": np.empty(sh, np.float32)}
-    zy = lambda a, b: (a[:, None] * b[None, :])[:, :, None]  # noqa: E731
-    np.multiply(zy(s(z, 41.0), s(y, 29.0)), 0.4 * s(x, 37.0)[None, None, :], out=st["phi"])
-    st["phi"] += np.float32(0.5)
-    np.multiply(zy(s(z, 17.0), np.ones(ny, np.float32)), 1e-3 * s(x, 53.0, 1.0)[None, None, :], out=st["rho_dev"])
-    for a, (Lx, Ly, Lz) in enumerate(((23.0, 31.0, 47.0), (27.0, 19.0, 43.0), (33.0, 25.0, 39.0))):
-        np.multiply(zy(s(z, Lz, a), s(y, Ly, 2 * a)), 0.02 * s(x, Lx, 0.5 + a)[None, None, :], out=st["u"][a])
-    for k in range(6):
-        np.multiply(zy(s(z, 29.0 + k, k), s(y, 23.0 + k)), 1e-4 * s(x, 31.0 + k, 0.3 * k)[None, None, :], out=st["P"][k])
-    return st
-
-
 def _sub_box(n, c, wall):
     """Index range [lo, lo + 9) along an axis of n nodes around node c, and whether it
     touches the lattice's own boundary (then the box takes wall faces on both sides;
@@ -474,7 +454,7 @@ def _sampled_step_parity(p, pts, label):
     from paper_2403_15773_amd.tslb import Simulation
     nx, ny, nz = p["nx"], p["ny"], p["nz"]
     _say("%s: building the synthetic state" % label)
-    st = _pattern_state(nx, ny, nz)
+    st = inputs.smooth_state(nx, ny, nz)
     boxes = []
     for (x, y, z) in pts:
         (xl, wx), (yl, wy), (zl, wz) = _sub_box(nx, x, True), _sub_box(ny, y, True), _sub_box(nz, z, True)
