@@ -5,6 +5,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -59,3 +60,19 @@ def test_committed_traffic_summaries_parse(name):
                 kv[k.strip()] = v.strip()
     assert len(kv["kernel_sources_sha256"]) == 16
     assert float(kv["hbm_bytes_per_launch"]) > 0
+
+
+def test_smooth_state_covers_every_node():
+    """inputs.smooth_state, the busy-state start the bench times beside the
+    headline: library layout (z, y, x), binary32, phi inside (0, 1) everywhere and
+    velocity, density and stress deviations of the stated sizes."""
+    from paper_2403_15773_amd import inputs
+    st = inputs.smooth_state(48, 40, 36)
+    assert st["phi"].shape == (36, 40, 48) and st["u"].shape == (3, 36, 40, 48) and st["P"].shape == (6, 36, 40, 48)
+    assert all(v.dtype == np.float32 for v in st.values())
+    assert 0.09 < st["phi"].min() and st["phi"].max() < 0.91
+    assert np.abs(st["u"]).max() <= 0.02 and np.abs(st["rho_dev"]).max() <= 1e-3 and np.abs(st["P"]).max() <= 1e-4
+    assert np.abs(st["u"]).max() > 0.015 and np.abs(st["P"]).max() > 5e-5
+    # no quiescent region: almost every node moves, and the phase field varies through the lattice
+    assert (np.abs(st["u"]).max(axis=0) < 1e-4).mean() < 0.01
+    assert st["phi"].std() > 0.1
