@@ -281,6 +281,20 @@ int tslb_step_kernel_times(tslb_ctx *ctx, float *ms, int64_t cap, int64_t *count
  * same step up to rounding, and the fused result does not depend on chunk_z. */
 int tslb_set_kernel(tslb_ctx *ctx, int kernel, int chunk_z);
 
+/* Height of the fused step's tiles (workgroups of 32 x rows destination
+ * columns): rows = 16 or 20 fixes it, 0 (the default) lets the library choose
+ * per lattice together with the z chunk, by the same cost model (a 20-row
+ * workgroup walks a plane in 1.18 times the time of a 16-row one and updates
+ * 1.25 times the columns; the height that gives each compute unit the least
+ * time wins).  20 rows serve the two-component step with equal densities only
+ * (TSLB_E_INVAL otherwise); the result is bitwise the same at either height.
+ * Not while the ctx is in a serving group (TSLB_E_STATE). */
+int tslb_set_tile(tslb_ctx *ctx, int rows);
+
+/* The tile height the fused step of ctx uses (16 or 20); TSLB_E_INVAL for a
+ * NULL ctx. */
+int tslb_tile_rows(const tslb_ctx *ctx);
+
 /* Free and total device memory of HIP device `device` in bytes (hipMemGetInfo):
  * what a serving loop admits requests against. */
 int tslb_device_memory(int32_t device, size_t *free_bytes, size_t *total_bytes);

@@ -260,6 +260,11 @@ int tslb_create(const tslb_params *p, tslb_ctx **out) {
             c->cu_count = cus;
     }
     derive_layout(p, c->geo, c->scales);
+    {
+        const FusedPlan pl = fused_plan(c);
+        c->plan_rows = pl.rows;
+        c->plan_lz = pl.lz;
+    }
     const Geo &g = c->geo;
     c->has_boundary = !(g.per[0] && g.per[1] && g.per[2]);
     Phys &ph = c->phys;
@@ -576,8 +581,26 @@ int tslb_set_kernel(tslb_ctx *c, int kernel, int chunk_z) {
     if (chunk_z < 0) return fail(c, TSLB_E_INVAL, "chunk_z must be >= 0");
     c->kernel = kernel;
     c->chunk_z = chunk_z;
+    const FusedPlan pl = fused_plan(c);
+    c->plan_rows = pl.rows;
+    c->plan_lz = pl.lz;
     return TSLB_OK;
 }
+
+int tslb_set_tile(tslb_ctx *c, int rows) {
+    if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");
+    NOT_IN_GROUP(c);
+    if (rows != 0 && rows != 16 && rows != 20) return fail(c, TSLB_E_INVAL, "rows must be 0, 16 or 20");
+    if (rows == 20 && !fused_wide_allowed(c))
+        return fail(c, TSLB_E_INVAL, "20-row tiles serve the two-component step with equal densities only");
+    c->tile_rows = rows;
+    const FusedPlan pl = fused_plan(c);
+    c->plan_rows = pl.rows;
+    c->plan_lz = pl.lz;
+    return TSLB_OK;
+}
+
+int tslb_tile_rows(const tslb_ctx *c) { return c ? c->plan_rows : TSLB_E_INVAL; }
 
 int tslb_set_timing(tslb_ctx *c, int enable) {
     if (!c) return fail(nullptr, TSLB_E_INVAL, "ctx is NULL");

@@ -43,9 +43,10 @@ struct tslb_group {
     int64_t completed = -1;      // every launch <= completed has finished
     hipEvent_t admit_ev = nullptr;
     std::string err;
-    // chunk bound of each launch class (storage type x component count, and the
-    // variable-density step), kept while the class's stepping members stay the same
-    static constexpr int kPlanClasses = 2 * 4 + 1;
+    // chunk bound of each launch class (storage type x {one component, two with
+    // 16-row tiles, two with 20-row tiles}, and the variable-density step), kept
+    // while the class's stepping members stay the same
+    static constexpr int kPlanClasses = 3 * 4 + 1;
     std::vector<const tslb_ctx *> plan_members[kPlanClasses];
     int plan_bound[kPlanClasses] = {};
 };
@@ -53,12 +54,15 @@ struct tslb_group {
 namespace {
 
 constexpr int kStorageTypes = 4;  // TSLB_STORE_FP32 .. TSLB_STORE_FP16Q
-// launch classes: storage type x component count, plus the variable-density
-// step (binary32, two components) as a class of its own
-constexpr int kClasses = 2 * kStorageTypes + 1;
-constexpr int kClassVD = 2 * kStorageTypes;
+// launch classes: storage type x {one component, two components on 16-row
+// tiles, two on 20-row tiles}, plus the variable-density step (binary32, two
+// components, 16 rows) as a class of its own
+constexpr int kClasses = 3 * kStorageTypes + 1;
+constexpr int kClassVD = 3 * kStorageTypes;
 static_assert(kClasses == tslb_group::kPlanClasses, "one chunk plan per launch class");
-int class_of(const tslb_ctx *c) { return c->vd ? kClassVD : 2 * c->storage + (c->phase ? 1 : 0); }
+int class_of(const tslb_ctx *c) {
+    return c->vd ? kClassVD : 3 * c->storage + (c->phase ? (fused_rows(c) == 20 ? 2 : 1) : 0);
+}
 
 int gfail(tslb_group *g, int code, const std::string &msg) {
     if (g)
@@ -306,7 +310,7 @@ int tslb_group_poll(tslb_group *g, tslb_ctx **done, int32_t cap, int32_t *ndone)
     }
     FusedDomain *h = g->h_tab[slot];
     int nrec = 0;
-    // one launch per class (storage type, component count) present
+    // one launch per class (storage type, component count, tile height; variable density) present
     int first[kClasses] = {}, count[kClasses] = {}, work[kClasses] = {};
     for (int cl = 0; cl < kClasses; ++cl) {
         first[cl] = nrec;
@@ -327,8 +331,9 @@ int tslb_group_poll(tslb_group *g, tslb_ctx **done, int32_t cap, int32_t *ndone)
     for (int cl = 0; cl < kClasses; ++cl)
         if (count[cl])
             GHIP_TRY(g, launch_step_fused_multi(g->d_tab[slot] + first[cl], count[cl], work[cl],
-                                                cl == kClassVD ? (int)ST_FP32 : cl >> 1,
-                                                cl == kClassVD || (cl & 1) != 0, cl == kClassVD, g->stream));
+                                                cl == kClassVD ? (int)ST_FP32 : cl / 3,
+                                                cl == kClassVD || cl % 3 != 0, cl == kClassVD,
+                                                cl != kClassVD && cl % 3 == 2 ? 20 : 16, g->stream));
     GHIP_TRY(g, hipEventRecord(g->ev[slot], g->stream));
     g->slot_launch[slot] = id;
     g->launches = id + 1;

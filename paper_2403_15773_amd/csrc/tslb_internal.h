@@ -82,6 +82,8 @@ struct tslb_ctx {
     tslb::Stats stats;
     int kernel = TSLB_KERNEL_FUSED;  // step kernel selected by tslb_set_kernel
     int chunk_z = 0;                 // z planes per workgroup of the fused kernel (0: automatic)
+    int tile_rows = 0;               // rows of a fused-step tile, 16 or 20 (0: automatic)
+    int plan_rows = 16, plan_lz = 1; // the fused step's tile height and z chunk (fused_plan, kept current)
     int cu_count = 256;              // compute units of the device
     tslb_group *group = nullptr;     // serving group that currently advances this ctx
     std::string err;
@@ -113,7 +115,16 @@ hipError_t launch_boundary(const tslb_ctx *c, StateView st, int64_t step, hipStr
 hipError_t launch_step(const tslb_ctx *c, StateView in, StateView out, int64_t step_next, hipStream_t s);
 hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int lz, int64_t step_next,
                              hipStream_t s);
+// Tile height (16 or 20 rows) and z chunk of the fused step of ctx c.
+struct FusedPlan {
+    int rows = 16;
+    int lz = 1;
+};
+FusedPlan fused_plan(const tslb_ctx *c);
 int fused_chunk(const tslb_ctx *c);
+int fused_rows(const tslb_ctx *c);
+// Whether the 20-row tile serves ctx c (two components, equal densities).
+bool fused_wide_allowed(const tslb_ctx *c);
 // Describe one step of ctx c (in -> out) as a domain of a multi-domain launch
 // whose work items start at work_begin; lz > 0 fixes the z chunk (else the
 // lattice's own choice).
@@ -121,10 +132,10 @@ FusedDomain fused_domain(const tslb_ctx *c, StateView in, StateView out, int64_t
                          int lz = 0);
 // Work items of one fused step of ctx c with z chunk lz.
 int fused_work_items(const tslb_ctx *c, int lz);
-// One fused step of every domain of a device table (all of one storage type and
-// component count).
+// One fused step of every domain of a device table (all of one storage type,
+// component count, density model and tile height).
 hipError_t launch_step_fused_multi(const FusedDomain *doms, int ndom, int total_work, int storage, bool phase,
-                                   bool vd, hipStream_t s);
+                                   bool vd, int rows, hipStream_t s);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
 hipError_t launch_diagnostics(const tslb_ctx *c, StateView st, const Scratch &sc, hipStream_t s);
 size_t diagnostics_blocks(const tslb_ctx *c);

@@ -48,29 +48,42 @@
 namespace tslb {
 namespace fused {
 
-constexpr int TX = 32, TY = 16;
-constexpr int SX = TX + 2, SY = TY + 2, NSRC = SX * SY;   // sources: 34 x 18
-constexpr int GX = TX + 4, GY = TY + 4, NGEO = GX * GY;   // geometry: 36 x 20
-constexpr int PX = TX + 6, PY = TY + 6, NPHI = PX * PY;   // phase field: 38 x 22
-constexpr int NDST = TX * TY;                              // 512
-constexpr int NT = 640;                                    // threads per workgroup
-constexpr int NXCH = 35;                                   // exchange slots per source (two components)
-constexpr int NXCH1 = 28;                                  // exchange slots per source (one component)
-
-static_assert(NSRC <= NT && NDST <= NSRC, "tile does not fit the workgroup");
-static_assert(NPHI <= 2 * NT && NGEO <= 2 * NT, "staging loops assume two items per thread");
+// Tile shapes.  A workgroup owns TX x TY destination columns; its sources, the
+// geometry and the staged phase field cover the tile plus a halo of 1, 2 and 3
+// columns.  Two heights: 16 rows with 640 threads (10 waves) and 20 rows with
+// 768 threads (12 waves, three on every SIMD, less halo per column), chosen per
+// lattice by the host (fused_plan); the one-component and variable-density
+// steps take 16 rows.
+template <int ROWS> struct Tile {
+    static constexpr int TX = 32, TY = ROWS;
+    static constexpr int SX = TX + 2, SY = TY + 2, NSRC = SX * SY;   // sources: 34 x 18 or 34 x 22
+    static constexpr int GX = TX + 4, GY = TY + 4, NGEO = GX * GY;   // geometry: 36 x 20 or 36 x 24
+    static constexpr int PX = TX + 6, PY = TY + 6, NPHI = PX * PY;   // phase field: 38 x 22 or 38 x 26
+    static constexpr int NDST = TX * TY;                              // 512 or 640
+    static constexpr int NT = ROWS == 16 ? 640 : 768;                 // threads per workgroup
+    static_assert(ROWS == 16 || ROWS == 20, "tile heights: 16 or 20 rows");
+    static_assert(NSRC <= NT && NDST <= NSRC, "tile does not fit the workgroup");
+    static_assert(NPHI <= 2 * NT && NGEO <= 2 * NT, "staging loops assume two items per thread");
+};
+constexpr int NXCH = 35;   // exchange slots per source (two components)
+constexpr int NXCH1 = 28;  // exchange slots per source (one component)
 
 // LDS of a workgroup: PH = two components (with the phase field), else one.
-template <bool PH> struct Smem;
-template <> struct Smem<true> {
-    int32_t phi[4][NPHI];      // fixed-point phase field, ring of 4 planes
-    float n[3][3][NGEO];       // unit normal, ring of 3 planes
-    float G[3][3][NSRC];       // gradient on the source region, ring of 3 planes
-    float xch[NXCH][NSRC];     // populations crossing columns
+// The gradient ring holds G itself for the variable-density step (its forces
+// take G directly), else only |G| + eps: the force is rebuilt as n (|G| + eps)
+// from the stored normal, which keeps the 20-row tile within 160 KB of LDS.
+template <bool PH, bool VD, int ROWS> struct Smem {
+    using T = Tile<ROWS>;
+    int32_t phi[4][T::NPHI];           // fixed-point phase field, ring of 4 planes
+    float n[3][3][T::NGEO];            // unit normal, ring of 3 planes
+    float G[3][VD ? 3 : 1][T::NSRC];   // gradient (VD) or |G| + eps on the source region, ring of 3 planes
+    float xch[NXCH][T::NSRC];          // populations crossing columns
 };
-template <> struct Smem<false> {
-    float xch[NXCH1][NSRC];    // populations crossing columns
+template <bool VD, int ROWS> struct Smem<false, VD, ROWS> {
+    float xch[NXCH1][Tile<ROWS>::NSRC];  // populations crossing columns
 };
+static_assert(sizeof(Smem<true, false, 20>) <= 160 * 1024 && sizeof(Smem<true, true, 16>) <= 160 * 1024,
+              "LDS of one workgroup");
 
 // 1-D three-point transform of (a_-, a_0, a_+) with weights (1/6, 2/3, 1/6):
 // m0 = sum w a, m1 = sum w c a, m2 = sum w (c^2 - 1/3) a, written relative to a_0.
@@ -154,10 +167,13 @@ __device__ __forceinline__ int xcd_work_item(int b, int nb) {
 // MULTI marks the multi-lattice kernel's instantiation: it keeps that kernel's
 // copy of the step apart from the single-lattice kernel's, whose code is
 // otherwise changed (and slowed) by the second user of the same instantiation.
-template <int ST, bool PH, bool G, bool MULTI, bool VD = false>
-__device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phys &ph, const Scales &sc,
+template <int ST, bool PH, bool G, bool MULTI, bool VD, int ROWS>
+__device__ __forceinline__ void step_fused(Smem<PH, VD, ROWS> &sm, const Geo &g, const Phys &ph, const Scales &sc,
                                            const StateView &in, const StateView &out, int lz, int tiles_x,
                                            int tiles_y, unsigned long long step_next, int w) {
+    using T = Tile<ROWS>;
+    constexpr int TX = T::TX, TY = T::TY, SX = T::SX, SY = T::SY, NSRC = T::NSRC, GX = T::GX, GY = T::GY,
+                  NGEO = T::NGEO, PX = T::PX, NPHI = T::NPHI, NDST = T::NDST, NT = T::NT;
     // exchange slots: 0-23 the x/y-crossing populations of the three z groups,
     // then (two components) 24-27 phase +-x, +-y; rho'; phase rest, +z, -z;
     // and the three populations of velocity (0, 0, c_z)
@@ -225,14 +241,24 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
     // 1, 5, 9) and SIMDs 2 and 3 two.  So waves 0-7 take one item each and the
     // NGEO - 512 remaining items go to waves 2, 3, 6 and 7: every SIMD then
     // issues about the same number of instructions in that phase.
-    static_assert(NDST == 512 && NGEO - NDST <= 256, "geometry item map assumes 8 destination waves");
+    // With 20 rows (12 waves, three sources on every SIMD) every thread takes one
+    // item and the NGEO - 768 others go to the two waves whose source work is
+    // lightest (wave 11 holds the last 44 sources).
     static_assert(GX >= 32 && GX < 64, "geometry rows are split into 32 + (GX - 32) columns");
     int geo_item[2];
-    geo_item[0] = t < NDST ? t : -1;
-    {
+    if constexpr (TY == 16) {
+        static_assert(NDST == 512 && NGEO - NDST <= 256, "geometry item map assumes 8 destination waves");
+        geo_item[0] = t < NDST ? t : -1;
         const int wv = t >> 6, lane = t & 63;
         const int rank = wv == 2 ? 0 : wv == 3 ? 1 : wv == 6 ? 2 : wv == 7 ? 3 : -1;
         const int i = NDST + rank * 64 + lane;
+        geo_item[1] = (rank >= 0 && i < NGEO) ? i : -1;
+    } else {
+        static_assert(NT <= NGEO && NGEO - NT <= 128, "geometry item map assumes one item per thread plus two waves");
+        geo_item[0] = t;
+        const int wv = t >> 6, lane = t & 63;
+        const int rank = wv == 10 ? 0 : wv == 11 ? 1 : -1;
+        const int i = NT + rank * 64 + lane;
         geo_item[1] = (rank >= 0 && i < NGEO) ? i : -1;
     }
 
@@ -351,6 +377,11 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
                     const int zr = r;
                     const bool bnd = src_bnd_xy || (!g.per[2] && (zr <= 0 || zr >= g.nz - 1));
                     const float a = bnd ? 0.f : -sigma * kap;
+                    const float *nr = &sm.n[(it + 1) % 3][0][0];  // plane r
+                    const int c = (sy + 1) * GX + (sx + 1);
+                    n0 = nr[c];
+                    n1 = nr[NGEO + c];
+                    n2 = nr[2 * NGEO + c];
                     const float *Gs = &sm.G[(it + 1) % 3][0][0];  // plane r
                     if constexpr (VD) {
                         Gx = Gs[sidx];
@@ -361,15 +392,11 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
                         F1 = a * Gy;
                         F2 = a * Gz;
                     } else {
-                        F0 = a * Gs[sidx];
-                        F1 = a * Gs[NSRC + sidx];
-                        F2 = a * Gs[2 * NSRC + sidx];
+                        const float ag = a * Gs[sidx];  // G = n (|G| + eps)
+                        F0 = ag * n0;
+                        F1 = ag * n1;
+                        F2 = ag * n2;
                     }
-                    const float *nr = &sm.n[(it + 1) % 3][0][0];  // plane r
-                    const int c = (sy + 1) * GX + (sx + 1);
-                    n0 = nr[c];
-                    n1 = nr[NGEO + c];
-                    n2 = nr[2 * NGEO + c];
                     phis = sm.phi[(it - 2) & 3][(sy + 2) * PX + (sx + 2)];
                 }
             }
@@ -552,7 +579,8 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
                             if (cz) G2 = fmaf(w * cz, d, G2);
                         }
                 // hardware square root (1 ulp) and a refined reciprocal: |G| + eps >= eps
-                const float inv = recip(__builtin_amdgcn_sqrtf(fmaf(G0, G0, fmaf(G1, G1, G2 * G2))) + eps);
+                const float den = __builtin_amdgcn_sqrtf(fmaf(G0, G0, fmaf(G1, G1, G2 * G2))) + eps;
+                const float inv = recip(den);
                 float *n = &sm.n[it % 3][0][0];
                 n[gi] = G0 * inv;
                 n[NGEO + gi] = G1 * inv;
@@ -561,9 +589,13 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
                 if (ssx >= 0 && ssx < SX && ssy >= 0 && ssy < SY) {
                     float *Gs = &sm.G[it % 3][0][0];
                     const int si = ssy * SX + ssx;
-                    Gs[si] = G0;
-                    Gs[NSRC + si] = G1;
-                    Gs[2 * NSRC + si] = G2;
+                    if constexpr (VD) {
+                        Gs[si] = G0;
+                        Gs[NSRC + si] = G1;
+                        Gs[2 * NSRC + si] = G2;
+                    } else {
+                        Gs[si] = den;
+                    }
                 }
             }
         }
@@ -692,19 +724,20 @@ __device__ __forceinline__ void step_fused(Smem<PH> &sm, const Geo &g, const Phy
 }
 
 
-template <int ST, bool PH, bool VD = false>
-__global__ __launch_bounds__(NT) void k_step_fused(Geo g, Phys ph, Scales sc, StateView in, StateView out, int lz,
-                                                   int tiles_x, int tiles_y, unsigned long long step_next) {
-    __shared__ Smem<PH> sm;
-    step_fused<ST, PH, false, false, VD>(sm, g, ph, sc, in, out, lz, tiles_x, tiles_y, step_next,
-                                         xcd_work_item(blockIdx.x, gridDim.x));
+template <int ST, bool PH, bool VD, int ROWS>
+__global__ __launch_bounds__(Tile<ROWS>::NT) void k_step_fused(Geo g, Phys ph, Scales sc, StateView in, StateView out,
+                                                               int lz, int tiles_x, int tiles_y,
+                                                               unsigned long long step_next) {
+    __shared__ Smem<PH, VD, ROWS> sm;
+    step_fused<ST, PH, false, false, VD, ROWS>(sm, g, ph, sc, in, out, lz, tiles_x, tiles_y, step_next,
+                                               xcd_work_item(blockIdx.x, gridDim.x));
 }
 
 // Several lattices in one launch: the work items of domain k are
 // [work_begin, work_begin + tiles * chunks); domains are sorted by work_begin.
-template <int ST, bool PH, bool VD = false>
-__global__ __launch_bounds__(NT) void k_step_fused_multi(const FusedDomain *__restrict__ doms, int ndom) {
-    __shared__ Smem<PH> sm;
+template <int ST, bool PH, bool VD, int ROWS>
+__global__ __launch_bounds__(Tile<ROWS>::NT) void k_step_fused_multi(const FusedDomain *__restrict__ doms, int ndom) {
+    __shared__ Smem<PH, VD, ROWS> sm;
     const int w = xcd_work_item(blockIdx.x, gridDim.x);
     int lo = 0, hi = ndom - 1;
     while (lo < hi) {
@@ -744,54 +777,96 @@ __global__ __launch_bounds__(NT) void k_step_fused_multi(const FusedDomain *__re
     in.mom = d.in.mom; in.phi = d.in.phi; out.mom = d.out.mom; out.phi = d.out.phi;
     const int lz = d.lz, tx = d.tiles_x, ty = d.tiles_y, wb = d.work_begin;
     const unsigned long long sn = d.step_next;
-    step_fused<ST, PH, (ST == ST_FP32), true, VD>(sm, g, ph, sc, in, out, lz, tx, ty, sn, w - wb);
+    step_fused<ST, PH, (ST == ST_FP32), true, VD, ROWS>(sm, g, ph, sc, in, out, lz, tx, ty, sn, w - wb);
 }
 
 }  // namespace fused
 
-// z planes per workgroup: the fixed choice of tslb_set_kernel, else the chunk
-// length that minimises a compute unit's share of the work.  A workgroup on a
-// chunk of lz planes walks lz + 6 planes (the pipeline refills its rings), and
-// the W work items give each CU ceil(W / CUs) of them, so the cost is
-// ceil(W / CUs) (lz + 6): long chunks recompute less halo, short ones keep
-// every unit busy; ties go to the shorter chunk.  Chunks are at most kMaxChunk
-// planes: workgroups that share halo columns run side by side, but over a long
-// chunk they drift apart in z and their shared halo planes leave L2 before
-// the neighbour reads them (HBM reads 1.48x the state at 2048 planes on a
-// 512 x 512 x 2048 lattice, against 1.06x at 64 on 128 x 128 x 512).
+// Tile height and z planes per workgroup.  A workgroup on a chunk of lz planes
+// walks lz + 6 planes (the pipeline refills its rings), and the W work items of
+// a launch give each CU ceil(W / CUs) of them, so the cost of a plan is
+// ceil(W / CUs) (lz + 6) c, with c the time of one pipeline plane of a
+// workgroup: 1 for 16 rows and kWideCost for 20 rows (measured on the
+// 512 x 512 x 2048 jet: a 32 x 20 workgroup walks a plane in 1.18 times the
+// time of a 32 x 16 one and updates 1.25 times the columns).  Long chunks
+// recompute less halo, short ones keep every unit busy; ties go to the shorter
+// chunk, then to 16 rows.  Chunks are at most kMaxChunk planes: workgroups that
+// share halo columns run side by side, but over a long chunk they drift apart
+// in z and their shared halo planes leave L2 before the neighbour reads them
+// (HBM reads 1.48x the state at 2048 planes on a 512 x 512 x 2048 lattice,
+// against 1.06x at 64 on 128 x 128 x 512).  20 rows serve the two-component
+// step with equal densities; the one-component step (whose 16-row workgroups
+// fit twice in a CU's LDS) and the variable-density step take 16.  A height or
+// chunk length fixed with tslb_set_tile / tslb_set_kernel is taken as given.
 constexpr int kMaxChunk = 128;
+constexpr double kWideCost = 1.18;
 
-int fused_chunk(const tslb_ctx *c) {
-    using namespace fused;
-    if (c->chunk_z > 0) return c->chunk_z;
-    const long long tiles = (long long)((c->geo.nx + TX - 1) / TX) * ((c->geo.ny + TY - 1) / TY);
+bool fused_wide_allowed(const tslb_ctx *c) { return c->phase && !c->vd; }
+
+namespace {
+
+int tiles_of(const tslb_ctx *c, int rows) {
+    return ((c->geo.nx + fused::Tile<16>::TX - 1) / fused::Tile<16>::TX) * ((c->geo.ny + rows - 1) / rows);
+}
+
+// Cheapest chunk length for `rows` and its cost (in 16-row plane times).
+double best_chunk(const tslb_ctx *c, int rows, int *lz_out) {
+    const long long tiles = tiles_of(c, rows);
     const long long cus = std::max(1, c->cu_count);
     const int nz = c->geo.nz;
+    const double f = rows == 16 ? 1.0 : kWideCost;
+    auto cost_of = [&](int lz) {
+        const long long w = tiles * ((nz + lz - 1) / lz);
+        return (double)((w + cus - 1) / cus) * (double)(lz + 6) * f;
+    };
+    if (c->chunk_z > 0) {
+        *lz_out = c->chunk_z;
+        return cost_of(c->chunk_z);
+    }
     int best_lz = std::min(nz, 4);
-    long long best_cost = -1;
+    double best = -1.0;
     for (int k = 1; k <= nz; ++k) {  // k chunks of ceil(nz / k) planes
         const int lz = (nz + k - 1) / k;
         if (lz < 4 && k > 1) break;
         if (k > 1 && lz == (nz + k - 2) / (k - 1)) continue;  // same length as k - 1 chunks
         if (lz > kMaxChunk) continue;
-        const long long w = tiles * ((nz + lz - 1) / lz);
-        const long long cost = (w + cus - 1) / cus * (long long)(lz + 6);
-        if (best_cost < 0 || cost <= best_cost) {
-            best_cost = cost;
+        const double cost = cost_of(lz);
+        if (best < 0 || cost <= best) {
+            best = cost;
             best_lz = lz;
         }
     }
-    return best_lz;
+    *lz_out = best_lz;
+    return best < 0 ? cost_of(best_lz) : best;
 }
 
+}  // namespace
+
+FusedPlan fused_plan(const tslb_ctx *c) {
+    FusedPlan pl;
+    int lz16 = 0, lz20 = 0;
+    const double c16 = best_chunk(c, 16, &lz16);
+    pl.rows = 16;
+    pl.lz = lz16;
+    if (!fused_wide_allowed(c) || c->tile_rows == 16) return pl;
+    const double c20 = best_chunk(c, 20, &lz20);
+    if (c->tile_rows == 20 || c20 < c16) {
+        pl.rows = 20;
+        pl.lz = lz20;
+    }
+    return pl;
+}
+
+int fused_chunk(const tslb_ctx *c) { return c->plan_lz; }
+
+int fused_rows(const tslb_ctx *c) { return c->plan_rows; }
+
 int fused_work_items(const tslb_ctx *c, int lz) {
-    using namespace fused;
-    return ((c->geo.nx + TX - 1) / TX) * ((c->geo.ny + TY - 1) / TY) * ((c->geo.nz + lz - 1) / lz);
+    return tiles_of(c, fused_rows(c)) * ((c->geo.nz + lz - 1) / lz);
 }
 
 FusedDomain fused_domain(const tslb_ctx *c, StateView in, StateView out, int64_t step_next, int work_begin,
                          int lz) {
-    using namespace fused;
     FusedDomain d;
     d.g = c->geo;
     d.ph = c->phys;
@@ -799,9 +874,9 @@ FusedDomain fused_domain(const tslb_ctx *c, StateView in, StateView out, int64_t
     d.in = in;
     d.out = out;
     d.step_next = (unsigned long long)step_next;
-    d.lz = lz > 0 ? lz : fused_chunk(c);
-    d.tiles_x = (c->geo.nx + TX - 1) / TX;
-    d.tiles_y = (c->geo.ny + TY - 1) / TY;
+    d.lz = lz > 0 ? lz : c->plan_lz;
+    d.tiles_x = (c->geo.nx + fused::Tile<16>::TX - 1) / fused::Tile<16>::TX;
+    d.tiles_y = (c->geo.ny + c->plan_rows - 1) / c->plan_rows;
     d.work_begin = work_begin;
     d.work_count = d.tiles_x * d.tiles_y * ((c->geo.nz + d.lz - 1) / d.lz);
     return d;
@@ -810,40 +885,43 @@ FusedDomain fused_domain(const tslb_ctx *c, StateView in, StateView out, int64_t
 // Launch the fused step over the whole lattice.
 namespace {
 
-template <int ST, bool PH, bool VD = false>
+template <int ST, bool PH, bool VD, int ROWS>
 void launch_one(unsigned blocks, hipStream_t s, const tslb_ctx *c, StateView in, StateView out, int lz, int tiles_x,
                 int tiles_y, unsigned long long sn) {
     using namespace fused;
-    hipLaunchKernelGGL((k_step_fused<ST, PH, VD>), dim3(blocks), dim3(NT), 0, s, c->geo, c->phys, c->scales, in, out,
-                       lz, tiles_x, tiles_y, sn);
+    hipLaunchKernelGGL((k_step_fused<ST, PH, VD, ROWS>), dim3(blocks), dim3(Tile<ROWS>::NT), 0, s, c->geo, c->phys,
+                       c->scales, in, out, lz, tiles_x, tiles_y, sn);
 }
 
-template <int ST, bool PH, bool VD = false>
+template <int ST, bool PH, bool VD, int ROWS>
 void launch_multi(unsigned blocks, hipStream_t s, const FusedDomain *doms, int ndom) {
     using namespace fused;
-    hipLaunchKernelGGL((k_step_fused_multi<ST, PH, VD>), dim3(blocks), dim3(NT), 0, s, doms, ndom);
+    hipLaunchKernelGGL((k_step_fused_multi<ST, PH, VD, ROWS>), dim3(blocks), dim3(Tile<ROWS>::NT), 0, s, doms, ndom);
 }
 
 }  // namespace
 
 hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int lz, int64_t step_next,
                              hipStream_t s) {
-    using namespace fused;
-    const int tiles_x = (c->geo.nx + TX - 1) / TX, tiles_y = (c->geo.ny + TY - 1) / TY;
+    const int rows = fused_rows(c);
+    const int tiles_x = (c->geo.nx + fused::Tile<16>::TX - 1) / fused::Tile<16>::TX;
+    const int tiles_y = (c->geo.ny + rows - 1) / rows;
     const int chunks = (c->geo.nz + lz - 1) / lz;
     const unsigned blocks = (unsigned)tiles_x * tiles_y * chunks;
     const unsigned long long sn = (unsigned long long)step_next;
-    if (c->vd) {  // variable density: binary32 storage, two components (validated at creation)
-        if (c->storage != ST_FP32 || !c->phase) return hipErrorInvalidValue;
-        launch_one<ST_FP32, true, true>(blocks, s, c, in, out, lz, tiles_x, tiles_y, sn);
+    if (c->vd) {  // variable density: binary32 storage, two components, 16 rows (validated at creation)
+        if (c->storage != ST_FP32 || !c->phase || rows != 16) return hipErrorInvalidValue;
+        launch_one<ST_FP32, true, true, 16>(blocks, s, c, in, out, lz, tiles_x, tiles_y, sn);
         return hipGetLastError();
     }
 #define TSLB_FUSED_CASE(ST)                                                                            \
     case ST:                                                                                           \
-        if (c->phase)                                                                                  \
-            launch_one<ST, true>(blocks, s, c, in, out, lz, tiles_x, tiles_y, sn);                     \
+        if (!c->phase)                                                                                 \
+            launch_one<ST, false, false, 16>(blocks, s, c, in, out, lz, tiles_x, tiles_y, sn);         \
+        else if (rows == 20)                                                                           \
+            launch_one<ST, true, false, 20>(blocks, s, c, in, out, lz, tiles_x, tiles_y, sn);          \
         else                                                                                           \
-            launch_one<ST, false>(blocks, s, c, in, out, lz, tiles_x, tiles_y, sn);                    \
+            launch_one<ST, true, false, 16>(blocks, s, c, in, out, lz, tiles_x, tiles_y, sn);          \
         break;
     switch (c->storage) {
         TSLB_FUSED_CASE(ST_FP32)
@@ -858,20 +936,23 @@ hipError_t launch_step_fused(const tslb_ctx *c, StateView in, StateView out, int
 }
 
 hipError_t launch_step_fused_multi(const FusedDomain *doms, int ndom, int total_work, int storage, bool phase,
-                                   bool vd, hipStream_t s) {
+                                   bool vd, int rows, hipStream_t s) {
     if (ndom <= 0 || total_work <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)total_work;
     if (vd) {
-        if (storage != ST_FP32 || !phase) return hipErrorInvalidValue;
-        launch_multi<ST_FP32, true, true>(blocks, s, doms, ndom);
+        if (storage != ST_FP32 || !phase || rows != 16) return hipErrorInvalidValue;
+        launch_multi<ST_FP32, true, true, 16>(blocks, s, doms, ndom);
         return hipGetLastError();
     }
+    if (rows != 16 && (rows != 20 || !phase)) return hipErrorInvalidValue;
 #define TSLB_MULTI_CASE(ST)                                                                            \
     case ST:                                                                                           \
-        if (phase)                                                                                     \
-            launch_multi<ST, true>(blocks, s, doms, ndom);                                             \
+        if (!phase)                                                                                    \
+            launch_multi<ST, false, false, 16>(blocks, s, doms, ndom);                                 \
+        else if (rows == 20)                                                                           \
+            launch_multi<ST, true, false, 20>(blocks, s, doms, ndom);                                  \
         else                                                                                           \
-            launch_multi<ST, false>(blocks, s, doms, ndom);                                            \
+            launch_multi<ST, true, false, 16>(blocks, s, doms, ndom);                                  \
         break;
     switch (storage) {
         TSLB_MULTI_CASE(ST_FP32)

@@ -31,7 +31,7 @@ EXPORTS = [
     "tslb_group_create", "tslb_group_admit", "tslb_group_poll", "tslb_group_status", "tslb_group_destroy",
     "tslb_group_last_error", "tslb_stats_start", "tslb_stats_stop", "tslb_stats_get", "tslb_probe_projection",
     "tslb_set_state_rest", "tslb_step_kernel_times", "tslb_device_memory", "tslb_group_busy", "tslb_device_bytes",
-    "tslb_diagnostics_noalloc",
+    "tslb_diagnostics_noalloc", "tslb_set_tile", "tslb_tile_rows",
 ]
 KERNEL_FUSED, KERNEL_GATHER = 0, 1
 
@@ -105,6 +105,8 @@ def load_library(path: str = LIB_PATH):
             "tslb_last_step_kernel_ms": (ctypes.c_double, [vp]),
             "tslb_step_kernel_times": (ctypes.c_int, [vp, _F, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
             "tslb_set_kernel": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
+            "tslb_set_tile": (ctypes.c_int, [vp, ctypes.c_int]),
+            "tslb_tile_rows": (ctypes.c_int, [vp]),
             "tslb_copy_bandwidth": (ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, ctypes.c_int,
                                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
             "tslb_probe_projection": (ctypes.c_int, [ctypes.c_int32, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
@@ -362,6 +364,14 @@ class Simulation:
     def set_kernel(self, kernel="fused", chunk_z=0):
         k = {"fused": KERNEL_FUSED, "gather": KERNEL_GATHER}[kernel] if isinstance(kernel, str) else int(kernel)
         self._check(self.lib.tslb_set_kernel(self.h, k, int(chunk_z)))
+
+    def set_tile(self, rows=0):
+        """Fused-step tile height: 16 or 20 rows, 0 = the library's choice."""
+        self._check(self.lib.tslb_set_tile(self.h, int(rows)))
+
+    @property
+    def tile_rows(self):
+        return int(self.lib.tslb_tile_rows(self.h))
 
 
 class Group:
