@@ -234,33 +234,31 @@ __device__ __forceinline__ void step_fused(Smem<PH, VD, ROWS> &sm, const Geo &g,
         const int gy = wrap_or_clamp(y0 - 3 + py, g.ny, g.per[1]);
         col_phi[k] = (long long)gx + (long long)g.nx * gy;
     }
-    // geometry items (<= 2 per thread): centre (gx, gy) in the 36 x 20 region.
-    // Waves are placed on the four SIMDs round-robin (wave w on SIMD w % 4), and
-    // the geometry of the next plane is computed in the same phase as the
-    // collision, where SIMDs 0 and 1 already run three source waves (0, 4, 8 and
-    // 1, 5, 9) and SIMDs 2 and 3 two.  So waves 0-7 take one item each and the
-    // NGEO - 512 remaining items go to waves 2, 3, 6 and 7: every SIMD then
-    // issues about the same number of instructions in that phase.
-    // With 20 rows (12 waves, three sources on every SIMD) every thread takes one
-    // item and the NGEO - 768 others go to the two waves whose source work is
-    // lightest (wave 11 holds the last 44 sources).
+    // Geometry items (S2 of plane p): centre (gx, gy) in the GX x GY region.
+    // Waves are placed on the four SIMDs round-robin (wave w on SIMD w % 4).  The
+    // normal and gradient of plane p are first read in the next iteration, so an
+    // item may run in either phase: most run in phase A beside the sources, and
+    // the last 128 in phase B on the two waves that hold no destination (waves 8
+    // and 9 with 16 rows, 10 and 11 with 20), which would otherwise only wait at
+    // the barrier there.  16 rows: SIMDs 0 and 1 run three source waves (0, 4, 8
+    // and 1, 5, 9), SIMDs 2 and 3 two, so waves 0-7 take items 0-511 and waves
+    // 2 and 3 the next 80.  20 rows (three sources on every SIMD): threads 0-735
+    // take one item each.
     static_assert(GX >= 32 && GX < 64, "geometry rows are split into 32 + (GX - 32) columns");
-    int geo_item[2];
+    constexpr int NGEO_B = NT - NDST;      // phase-B items: one per thread without a destination
+    constexpr int NGEO_A = NGEO - NGEO_B;  // phase-A items
+    static_assert(NGEO_B == 128, "two waves without a destination");
+    int geo_a[2] = {-1, -1};
     if constexpr (TY == 16) {
-        static_assert(NDST == 512 && NGEO - NDST <= 256, "geometry item map assumes 8 destination waves");
-        geo_item[0] = t < NDST ? t : -1;
+        static_assert(NDST == 512 && NGEO_A == NDST + 80, "16-row geometry map: 512 + 80 items in phase A");
         const int wv = t >> 6, lane = t & 63;
-        const int rank = wv == 2 ? 0 : wv == 3 ? 1 : wv == 6 ? 2 : wv == 7 ? 3 : -1;
-        const int i = NDST + rank * 64 + lane;
-        geo_item[1] = (rank >= 0 && i < NGEO) ? i : -1;
+        geo_a[0] = t < NDST ? t : -1;
+        if ((wv == 2 || wv == 3) && lane < 40) geo_a[1] = NDST + (wv - 2) * 40 + lane;
     } else {
-        static_assert(NT <= NGEO && NGEO - NT <= 128, "geometry item map assumes one item per thread plus two waves");
-        geo_item[0] = t;
-        const int wv = t >> 6, lane = t & 63;
-        const int rank = wv == 10 ? 0 : wv == 11 ? 1 : -1;
-        const int i = NT + rank * 64 + lane;
-        geo_item[1] = (rank >= 0 && i < NGEO) ? i : -1;
+        static_assert(NGEO_A <= NT, "20-row geometry map: one phase-A item per thread");
+        geo_a[0] = t < NGEO_A ? t : -1;
     }
+    const int geo_b = t >= NDST ? NGEO_A + (t - NDST) : -1;
 
     const float omega1 = 1.0f - ph.omega;
     const float sigma = ph.sigma, gamma = ph.gamma, eps = ph.eps;
@@ -298,6 +296,59 @@ __device__ __forceinline__ void step_fused(Smem<PH, VD, ROWS> &sm, const Geo &g,
 #pragma unroll
         for (int k = 0; k < 2; ++k)
             if (phi_item[k] >= 0) v[k] = mem<G>(in.phi)[col_phi[k] + zoff];
+    };
+
+    // ---- S2: G and n of plane p from phi planes p-1, p, p+1 (slots it-1, it, it+1),
+    // one geometry item i ----
+    auto geometry_item = [&](int i, int it) {
+        if constexpr (PH) {
+            const int32_t *pm = sm.phi[(it + 3) & 3], *p0 = sm.phi[it & 3], *pp = sm.phi[(it + 1) & 3];
+            // items 0 .. 32 GY - 1 cover columns 0-31 of each row, one row per
+            // half-wave (contiguous LDS addresses, no bank conflicts); the
+            // rest cover columns 32 .. GX - 1
+            const int gxl = i < 32 * GY ? (i & 31) : 32 + (i - 32 * GY) % (GX - 32);
+            const int gyl = i < 32 * GY ? (i >> 5) : (i - 32 * GY) / (GX - 32);
+            const int gi = gyl * GX + gxl;  // position in the geometry region
+            const int c = (gyl + 1) * PX + (gxl + 1);  // centre in the phi region
+            float G0 = 0.f, G1 = 0.f, G2 = 0.f;
+#pragma unroll
+            for (int cz = -1; cz <= 1; ++cz)
+#pragma unroll
+                for (int cy = -1; cy <= 1; ++cy)
+#pragma unroll
+                    for (int cx = -1; cx <= 1; ++cx) {
+                        const bool lead = cx > 0 || (cx == 0 && (cy > 0 || (cy == 0 && cz > 0)));
+                        if (!lead) continue;
+                        const int32_t *pa = cz > 0 ? pp : (cz < 0 ? pm : p0);
+                        const int32_t *pb = cz > 0 ? pm : (cz < 0 ? pp : p0);
+                        const int32_t a = pa[c + cy * PX + cx];
+                        const int32_t bb = pb[c - cy * PX - cx];
+                        const float d = (float)(a - bb);
+                        const float w = 3.0f * w27(cx, cy, cz) * kPhiUlp;
+                        if (cx) G0 = fmaf(w * cx, d, G0);
+                        if (cy) G1 = fmaf(w * cy, d, G1);
+                        if (cz) G2 = fmaf(w * cz, d, G2);
+                    }
+            // hardware square root (1 ulp) and a refined reciprocal: |G| + eps >= eps
+            const float den = __builtin_amdgcn_sqrtf(fmaf(G0, G0, fmaf(G1, G1, G2 * G2))) + eps;
+            const float inv = recip(den);
+            float *n = &sm.n[it % 3][0][0];
+            n[gi] = G0 * inv;
+            n[NGEO + gi] = G1 * inv;
+            n[2 * NGEO + gi] = G2 * inv;
+            const int ssx = gxl - 1, ssy = gyl - 1;
+            if (ssx >= 0 && ssx < SX && ssy >= 0 && ssy < SY) {
+                float *Gs = &sm.G[it % 3][0][0];
+                const int si = ssy * SX + ssx;
+                if constexpr (VD) {
+                    Gs[si] = G0;
+                    Gs[NSRC + si] = G1;
+                    Gs[2 * NSRC + si] = G2;
+                } else {
+                    Gs[si] = den;
+                }
+            }
+        }
     };
 
     const int nit = (z1 - z0) + 6;
@@ -546,58 +597,10 @@ __device__ __forceinline__ void step_fused(Smem<PH, VD, ROWS> &sm, const Geo &g,
             }
         }
 
-        // ---- S2: G and n of plane p from phi planes p-1, p, p+1 (slots it-1, it, it+1) ----
+        // ---- S2, phase-A items ----
         if constexpr (PH) if (it >= 1 && it + 2 <= nit) {
-            const int32_t *pm = sm.phi[(it + 3) & 3], *p0 = sm.phi[it & 3], *pp = sm.phi[(it + 1) & 3];
-            for (int k = 0; k < 2; ++k) {
-                const int i = geo_item[k];
-                if (i < 0) continue;
-                // items 0 .. 32 GY - 1 cover columns 0-31 of each row, one row per
-                // half-wave (contiguous LDS addresses, no bank conflicts); the
-                // rest cover columns 32 .. GX - 1
-                const int gxl = i < 32 * GY ? (i & 31) : 32 + (i - 32 * GY) % (GX - 32);
-                const int gyl = i < 32 * GY ? (i >> 5) : (i - 32 * GY) / (GX - 32);
-                const int gi = gyl * GX + gxl;  // position in the geometry region
-                const int c = (gyl + 1) * PX + (gxl + 1);  // centre in the phi region
-                float G0 = 0.f, G1 = 0.f, G2 = 0.f;
-#pragma unroll
-                for (int cz = -1; cz <= 1; ++cz)
-#pragma unroll
-                    for (int cy = -1; cy <= 1; ++cy)
-#pragma unroll
-                        for (int cx = -1; cx <= 1; ++cx) {
-                            const bool lead = cx > 0 || (cx == 0 && (cy > 0 || (cy == 0 && cz > 0)));
-                            if (!lead) continue;
-                            const int32_t *pa = cz > 0 ? pp : (cz < 0 ? pm : p0);
-                            const int32_t *pb = cz > 0 ? pm : (cz < 0 ? pp : p0);
-                            const int32_t a = pa[c + cy * PX + cx];
-                            const int32_t bb = pb[c - cy * PX - cx];
-                            const float d = (float)(a - bb);
-                            const float w = 3.0f * w27(cx, cy, cz) * kPhiUlp;
-                            if (cx) G0 = fmaf(w * cx, d, G0);
-                            if (cy) G1 = fmaf(w * cy, d, G1);
-                            if (cz) G2 = fmaf(w * cz, d, G2);
-                        }
-                // hardware square root (1 ulp) and a refined reciprocal: |G| + eps >= eps
-                const float den = __builtin_amdgcn_sqrtf(fmaf(G0, G0, fmaf(G1, G1, G2 * G2))) + eps;
-                const float inv = recip(den);
-                float *n = &sm.n[it % 3][0][0];
-                n[gi] = G0 * inv;
-                n[NGEO + gi] = G1 * inv;
-                n[2 * NGEO + gi] = G2 * inv;
-                const int ssx = gxl - 1, ssy = gyl - 1;
-                if (ssx >= 0 && ssx < SX && ssy >= 0 && ssy < SY) {
-                    float *Gs = &sm.G[it % 3][0][0];
-                    const int si = ssy * SX + ssx;
-                    if constexpr (VD) {
-                        Gs[si] = G0;
-                        Gs[NSRC + si] = G1;
-                        Gs[2 * NSRC + si] = G2;
-                    } else {
-                        Gs[si] = den;
-                    }
-                }
-            }
+            for (int k = 0; k < 2; ++k)
+                if (geo_a[k] >= 0) geometry_item(geo_a[k], it);
         }
         __syncthreads();
 
@@ -621,6 +624,8 @@ __device__ __forceinline__ void step_fused(Smem<PH, VD, ROWS> &sm, const Geo &g,
                     if (phi_item[k] >= 0) sm.phi[(it + 2) & 3][phi_item[k]] = phi_next[k];
             }
         }
+        // ---- S2, phase-B items (the slots read are not the one staged above) ----
+        if constexpr (PH) if (geo_b >= 0 && it >= 1 && it + 2 <= nit) geometry_item(geo_b, it);
         if (it >= 4) {
             // ---- S5b/S6: gather at the destination and finish plane r - 1 ----
             if (is_dst) {
