@@ -243,22 +243,32 @@ __device__ __forceinline__ void step_fused(Smem<PH, VD, ROWS> &sm, const Geo &g,
     // the barrier there.  16 rows: SIMDs 0 and 1 run three source waves (0, 4, 8
     // and 1, 5, 9), SIMDs 2 and 3 two, so waves 0-7 take items 0-511 and waves
     // 2 and 3 the next 80.  20 rows (three sources on every SIMD): threads 0-735
-    // take one item each.
+    // take one item each.  The variable-density step (16 rows; its items store
+    // all of G) keeps every item in phase A, where that measured faster: waves
+    // 0-7 take items 0-511 and waves 2, 3, 6 and 7 the other 208.
     static_assert(GX >= 32 && GX < 64, "geometry rows are split into 32 + (GX - 32) columns");
-    constexpr int NGEO_B = NT - NDST;      // phase-B items: one per thread without a destination
-    constexpr int NGEO_A = NGEO - NGEO_B;  // phase-A items
-    static_assert(NGEO_B == 128, "two waves without a destination");
+    constexpr int NGEO_B = VD ? 0 : NT - NDST;  // phase-B items: one per thread without a destination
+    constexpr int NGEO_A = NGEO - NGEO_B;       // phase-A items
+    static_assert(VD || NGEO_B == 128, "two waves without a destination");
     int geo_a[2] = {-1, -1};
-    if constexpr (TY == 16) {
-        static_assert(NDST == 512 && NGEO_A == NDST + 80, "16-row geometry map: 512 + 80 items in phase A");
+    {
         const int wv = t >> 6, lane = t & 63;
-        geo_a[0] = t < NDST ? t : -1;
-        if ((wv == 2 || wv == 3) && lane < 40) geo_a[1] = NDST + (wv - 2) * 40 + lane;
-    } else {
-        static_assert(NGEO_A <= NT, "20-row geometry map: one phase-A item per thread");
-        geo_a[0] = t < NGEO_A ? t : -1;
+        if constexpr (TY == 16 && VD) {
+            static_assert(NDST == 512 && NGEO - NDST <= 256, "16-row geometry map: 512 + 4 waves of items");
+            const int rank = wv == 2 ? 0 : wv == 3 ? 1 : wv == 6 ? 2 : wv == 7 ? 3 : -1;
+            const int i = NDST + rank * 64 + lane;
+            geo_a[0] = t < NDST ? t : -1;
+            if (rank >= 0 && i < NGEO) geo_a[1] = i;
+        } else if constexpr (TY == 16) {
+            static_assert(NDST == 512 && NGEO_A == NDST + 80, "16-row geometry map: 512 + 80 items in phase A");
+            geo_a[0] = t < NDST ? t : -1;
+            if ((wv == 2 || wv == 3) && lane < 40) geo_a[1] = NDST + (wv - 2) * 40 + lane;
+        } else {
+            static_assert(!VD && NGEO_A <= NT, "20-row geometry map: one phase-A item per thread");
+            geo_a[0] = t < NGEO_A ? t : -1;
+        }
     }
-    const int geo_b = t >= NDST ? NGEO_A + (t - NDST) : -1;
+    const int geo_b = (NGEO_B > 0 && t >= NDST) ? NGEO_A + (t - NDST) : -1;
 
     const float omega1 = 1.0f - ph.omega;
     const float sigma = ph.sigma, gamma = ph.gamma, eps = ph.eps;
