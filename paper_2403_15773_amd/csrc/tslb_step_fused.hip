@@ -235,21 +235,25 @@ __device__ __forceinline__ void step_fused(Smem<PH, VD, ROWS> &sm, const Geo &g,
         col_phi[k] = (long long)gx + (long long)g.nx * gy;
     }
     // Geometry items (S2 of plane p): centre (gx, gy) in the GX x GY region.
-    // Waves are placed on the four SIMDs round-robin (wave w on SIMD w % 4).  The
-    // normal and gradient of plane p are first read in the next iteration, so an
-    // item may run in either phase: most run in phase A beside the sources, and
-    // the last 128 in phase B on the two waves that hold no destination (waves 8
-    // and 9 with 16 rows, 10 and 11 with 20), which would otherwise only wait at
-    // the barrier there.  16 rows: SIMDs 0 and 1 run three source waves (0, 4, 8
-    // and 1, 5, 9), SIMDs 2 and 3 two, so waves 0-7 take items 0-511 and waves
-    // 2 and 3 the next 80.  20 rows (three sources on every SIMD): threads 0-735
-    // take one item each.  The variable-density step (16 rows; its items store
-    // all of G) keeps every item in phase A, where that measured faster: waves
-    // 0-7 take items 0-511 and waves 2, 3, 6 and 7 the other 208.
+    // Waves are placed on the four SIMDs round-robin (wave w on SIMD w % 4), and
+    // each phase ends at a barrier.  The normal and gradient of plane p are first
+    // read in the next iteration, so an item may run in either phase.
+    // 16 rows: SIMDs 0 and 1 run three source waves (0, 4, 8 and 1, 5, 9), SIMDs
+    // 2 and 3 two, so in phase A waves 0-7 take items 0-511 and waves 2 and 3 the
+    // next 80; the last 128 run in phase B on waves 8 and 9, which have no
+    // destination.
+    // 20 rows: phase A holds three source waves on every SIMD, phase B three
+    // destination waves on SIMDs 0 and 1 but two on SIMDs 2 and 3, so threads
+    // 0-479 (two waves per SIMD) take one item in phase A, and in phase B waves 10
+    // and 11 (no destination) and waves 2, 3, 6 and 7 (before their destination)
+    // one item each.
+    // The variable-density step (16 rows; its items store all of G) keeps every
+    // item in phase A, where that measured faster: waves 0-7 take items 0-511 and
+    // waves 2, 3, 6 and 7 the other 208.
     static_assert(GX >= 32 && GX < 64, "geometry rows are split into 32 + (GX - 32) columns");
-    constexpr int NGEO_B = VD ? 0 : NT - NDST;  // phase-B items: one per thread without a destination
-    constexpr int NGEO_A = NGEO - NGEO_B;       // phase-A items
-    static_assert(VD || NGEO_B == 128, "two waves without a destination");
+    constexpr int NGEO_B = VD ? 0 : (TY == 16 ? NT - NDST : 384);  // phase-B items
+    constexpr int NGEO_A = NGEO - NGEO_B;                          // phase-A items
+    static_assert(VD || NT - NDST == 128, "two waves without a destination");
     int geo_a[2] = {-1, -1};
     {
         const int wv = t >> 6, lane = t & 63;
@@ -264,11 +268,16 @@ __device__ __forceinline__ void step_fused(Smem<PH, VD, ROWS> &sm, const Geo &g,
             geo_a[0] = t < NDST ? t : -1;
             if ((wv == 2 || wv == 3) && lane < 40) geo_a[1] = NDST + (wv - 2) * 40 + lane;
         } else {
-            static_assert(!VD && NGEO_A <= NT, "20-row geometry map: one phase-A item per thread");
+            static_assert(!VD && NGEO_A == 480, "20-row geometry map: waves 0-7 in phase A");
             geo_a[0] = t < NGEO_A ? t : -1;
         }
     }
-    const int geo_b = (NGEO_B > 0 && t >= NDST) ? NGEO_A + (t - NDST) : -1;
+    int geo_b = (NGEO_B > 0 && t >= NDST) ? NGEO_A + (t - NDST) : -1;  // waves without a destination
+    if constexpr (TY == 20) {  // and waves 2, 3, 6, 7, before their destination work
+        const int wv = t >> 6, lane = t & 63;
+        const int r4 = wv == 2 ? 0 : wv == 3 ? 1 : wv == 6 ? 2 : wv == 7 ? 3 : -1;
+        if (r4 >= 0) geo_b = NGEO_A + 128 + r4 * 64 + lane;
+    }
 
     const float omega1 = 1.0f - ph.omega;
     const float sigma = ph.sigma, gamma = ph.gamma, eps = ph.eps;
@@ -634,7 +643,8 @@ __device__ __forceinline__ void step_fused(Smem<PH, VD, ROWS> &sm, const Geo &g,
                     if (phi_item[k] >= 0) sm.phi[(it + 2) & 3][phi_item[k]] = phi_next[k];
             }
         }
-        // ---- S2, phase-B items (the slots read are not the one staged above) ----
+        // ---- S2, phase-B items, before any destination work (the slots read are not the
+        // one staged above) ----
         if constexpr (PH) if (geo_b >= 0 && it >= 1 && it + 2 <= nit) geometry_item(geo_b, it);
         if (it >= 4) {
             // ---- S5b/S6: gather at the destination and finish plane r - 1 ----
