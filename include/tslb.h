@@ -275,7 +275,8 @@ int tslb_step_kernel_times(tslb_ctx *ctx, float *ms, int64_t cap, int64_t *count
 
 /* Select the step kernel (TSLB_KERNEL_*) and, for the fused kernel, the number
  * of z planes a workgroup marches through: chunk_z >= 1 fixes it, 0 (the
- * default) lets the library choose per lattice (at most 128 planes, the length
+ * default) lets the library choose per lattice (at most 128 planes on 16-row
+ * tiles and 256 on 20-row tiles, the length
  * that minimises the rounds of workgroups per compute unit times the planes
  * each round walks, its chunk plus a pipeline of 6).  Both kernels compute the
  * same step up to rounding, and the fused result does not depend on chunk_z. */

@@ -815,15 +815,18 @@ __global__ __launch_bounds__(Tile<ROWS>::NT) void k_step_fused_multi(const Fused
 // 512 x 512 x 2048 jet: a 32 x 20 workgroup walks a plane in 1.18 times the
 // time of a 32 x 16 one and updates 1.25 times the columns).  Long chunks
 // recompute less halo, short ones keep every unit busy; ties go to the shorter
-// chunk, then to 16 rows.  Chunks are at most kMaxChunk planes: workgroups that
-// share halo columns run side by side, but over a long chunk they drift apart
-// in z and their shared halo planes leave L2 before the neighbour reads them
-// (HBM reads 1.48x the state at 2048 planes on a 512 x 512 x 2048 lattice,
-// against 1.06x at 64 on 128 x 128 x 512).  20 rows serve the two-component
+// chunk, then to 16 rows.  Chunks are capped (kMaxChunk16, kMaxChunk20 planes):
+// workgroups that share halo columns run side by side, but over a long chunk
+// they drift apart in z and their shared halo planes leave L2 before the
+// neighbour reads them (HBM reads 1.48x the state at 2048 planes on a
+// 512 x 512 x 2048 lattice, against 1.06x at 64 on 128 x 128 x 512).  The caps
+// are measured on that lattice: 16-row tiles gained nothing beyond 128 planes,
+// 20-row tiles ran 1.6 % faster at 256 than at 128 and slower at 342 or 683.
+// 20 rows serve the two-component
 // step with equal densities; the one-component step (whose 16-row workgroups
 // fit twice in a CU's LDS) and the variable-density step take 16.  A height or
 // chunk length fixed with tslb_set_tile / tslb_set_kernel is taken as given.
-constexpr int kMaxChunk = 128;
+constexpr int kMaxChunk16 = 128, kMaxChunk20 = 256;
 constexpr double kWideCost = 1.18;
 
 bool fused_wide_allowed(const tslb_ctx *c) { return c->phase && !c->vd; }
@@ -854,7 +857,7 @@ double best_chunk(const tslb_ctx *c, int rows, int *lz_out) {
         const int lz = (nz + k - 1) / k;
         if (lz < 4 && k > 1) break;
         if (k > 1 && lz == (nz + k - 2) / (k - 1)) continue;  // same length as k - 1 chunks
-        if (lz > kMaxChunk) continue;
+        if (lz > (rows == 16 ? kMaxChunk16 : kMaxChunk20)) continue;
         const double cost = cost_of(lz);
         if (best < 0 || cost <= best) {
             best = cost;
