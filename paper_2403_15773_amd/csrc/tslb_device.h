@@ -78,6 +78,10 @@ __device__ __forceinline__ typename MemView<G, T>::P mem(T *p) {
         return p;
 }
 
+// binary32 -> bfloat16 bits, rounded to nearest even (a NaN stays a quiet NaN):
+// one hardware conversion on gfx950 (v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint16_t bf16_bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
+
 template <int ST> struct Store;
 
 template <> struct Store<ST_FP32> {
@@ -98,12 +102,7 @@ template <> struct Store<ST_BF16> {
     static __device__ __forceinline__ float load(const T *p, long long i, float s) {
         return __uint_as_float((uint32_t)p[i] << 16) * s;
     }
-    // round to nearest even on the upper 16 bits (NaN kept quiet)
-    static __device__ __forceinline__ void store(T *p, long long i, float v, float inv_s) {
-        uint32_t b = __float_as_uint(v * inv_s);
-        uint32_t r = ((b & 0x7fffffffu) > 0x7f800000u) ? (b | 0x00400000u) : (b + 0x7fffu + ((b >> 16) & 1u));
-        p[i] = (uint16_t)(r >> 16);
-    }
+    static __device__ __forceinline__ void store(T *p, long long i, float v, float inv_s) { p[i] = bf16_bits(v * inv_s); }
 };
 
 // Bytes of the ten moment planes of one state buffer (planes of ld elements),
@@ -178,9 +177,7 @@ __device__ __forceinline__ void store_moment(void *mom, long long ld, int p, lon
     } else if constexpr (ST == ST_FP16) {
         store_nt(&mem<G>((_Float16 *)mom + p * ld)[id], (_Float16)(v * ((p >= 1 && p < 4) ? sc.inv_s1 : sc.inv_s2)));
     } else {
-        const uint32_t b = __float_as_uint(v * ((p >= 1 && p < 4) ? sc.inv_s1 : sc.inv_s2));
-        const uint32_t r = ((b & 0x7fffffffu) > 0x7f800000u) ? (b | 0x00400000u) : (b + 0x7fffu + ((b >> 16) & 1u));
-        store_nt(&mem<G>((uint16_t *)mom + p * ld)[id], (uint16_t)(r >> 16));
+        store_nt(&mem<G>((uint16_t *)mom + p * ld)[id], bf16_bits(v * ((p >= 1 && p < 4) ? sc.inv_s1 : sc.inv_s2)));
     }
 }
 

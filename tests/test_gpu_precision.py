@@ -178,3 +178,42 @@ def test_jet_16_bit_storage_against_binary32(we):
         assert l2u <= L2_BOUND[storage] and l2phi <= L2_BOUND[storage]
         assert abs(pen - pen32) <= INTEGRAL_BOUND[storage] * pen32
         assert abs(uz - uz32) <= INTEGRAL_BOUND[storage] * abs(uz32)
+
+
+def _bf16_rne_bits(x):
+    """binary32 -> bfloat16 bits by round to nearest, ties to even, on the upper
+    16 bits of the binary32 word (finite inputs)."""
+    b = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    return ((b + 0x7FFF + ((b >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+def test_bf16_store_rounds_to_nearest_even():
+    """The BF16 store (the hardware conversion of gfx950) against the definition
+    of round to nearest even: exact ties with even and odd kept bits, one unit
+    on either side of a tie, exact values and random words, both signs, from
+    1e-30 to 1e3.  rho' is stored scaled by 1/U^2, so U = 1 stores it as given
+    in plane 0 of the raw state."""
+    from paper_2403_15773_amd.tslb import Simulation
+    n = 16
+    rng = np.random.default_rng(11)
+    N = n * n * n
+    hi = rng.integers(0, 1 << 16, N, dtype=np.uint64)
+    expo = rng.integers(27, 137, N, dtype=np.uint64)  # about 1e-30 .. 1e3
+    lows = np.array([0x8000, 0x7FFF, 0x8001, 0x0000, 0xFFFF], np.uint64)
+    low = np.where(np.arange(N) % 6 < 5, lows[np.arange(N) % 6 % 5],
+                   rng.integers(0, 1 << 16, N, dtype=np.uint64)).astype(np.uint64)
+    sign = ((np.arange(N) // 6) % 2).astype(np.uint64)
+    words = (sign << 31) | (expo << 23) | ((hi & 0x7F) << 16) | low
+    rho = words.astype(np.uint32).view(np.float32).reshape(n, n, n).copy()
+    assert np.all(np.isfinite(rho)) and np.all(np.abs(rho) < 1e4)
+    zero3 = np.zeros((3, n, n, n), np.float32)
+    zero6 = np.zeros((6, n, n, n), np.float32)
+    _say("bf16 store: %d words, %d exact ties" % (N, int(np.sum((low == 0x8000)))))
+    with Simulation(nx=n, ny=n, nz=n, nu=0.05, components=1, storage="bf16", u_scale=1.0) as s:
+        s.set_state(rho_dev=rho, u=zero3, P=zero6)
+        raw = s.get_state_raw().view(np.uint16)
+    got = raw[:N]
+    want = _bf16_rne_bits(rho.reshape(-1))
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, "first mismatches: " + ", ".join(
+        "%08x -> %04x (want %04x)" % (int(words[i]), int(got[i]), int(want[i])) for i in bad[:5])
