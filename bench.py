@@ -29,6 +29,7 @@ import ctypes
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -66,6 +67,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-oracle sample budget (0 = skip)")
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the copy-kernel ceiling probe (0 = skip)")
     ap.add_argument("--kernel", default="fused", choices=["fused", "gather"])
+    ap.add_argument("--repeats", type=int, default=4,
+                    help="further timed runs of the headline's steps after its timed region (median of all reported)")
     ap.add_argument("--probe", type=int, default=1, help="time the projection on ALU and matrix cores (0 = skip)")
     return ap.parse_args()
 
@@ -133,10 +136,12 @@ def measured_traffic(workload, storage):
         return None
 
 
-def run_lattice(name, storage, steps, warmup, kernel="fused", smooth=False):
+def run_lattice(name, storage, steps, warmup, kernel="fused", smooth=False, repeats=0):
     """Time `steps` steps of workload `name`; returns the measurements.  smooth:
     start from inputs.smooth_state (no quiescent node) instead of the workload's
-    own initial state."""
+    own initial state.  repeats: after the timed region, time that many more
+    batches of `steps` steps of the same lattice (continuing its run), each by
+    the wall clock around it, for the spread of whole timed runs."""
     import numpy as np
 
     from paper_2403_15773_amd import inputs
@@ -169,6 +174,15 @@ def run_lattice(name, storage, steps, warmup, kernel="fused", smooth=False):
     t1 = time.perf_counter()
     kernel_ms = sim.last_step_kernel_ms()
     times = sim.step_kernel_times()
+    rep = []
+    if repeats > 0:
+        sim.set_timing(False)
+        for _ in range(repeats):
+            sim.sync()
+            r0 = time.perf_counter()
+            sim.step(steps)
+            sim.sync()
+            rep.append(nodes * steps / (time.perf_counter() - r0) / 1e9)
     diag = sim.diagnostics()
     sim.close()
     T = t1 - t0
@@ -179,7 +193,7 @@ def run_lattice(name, storage, steps, warmup, kernel="fused", smooth=False):
     spread = {"median": float(np.median(times)), "min": float(times.min()), "max": float(times.max()),
               "launches": int(times.size)} if times.size else None
     return {"p": p, "st": st, "nodes": nodes, "T": T, "glups": nodes * steps / T / 1e9, "kernel_ms": kernel_ms,
-            "kernel_ms_spread": spread, "achieved": achieved, "bpn": bpn, "finite": diag["finite"]}
+            "kernel_ms_spread": spread, "achieved": achieved, "bpn": bpn, "finite": diag["finite"], "repeats": rep}
 
 
 def serving(n_requests):
@@ -297,7 +311,7 @@ def main():
         gbps, cms = copy_bandwidth(a.copy_mib << 20, iters=20)
         copy = {"gbps": gbps, "ms": cms, "bytes_moved": 2 * (a.copy_mib << 20)}
         log("copy-kernel ceiling %.0f GB/s (%d MiB read + written, %.3f ms)" % (gbps, 2 * a.copy_mib, cms))
-    m = run_lattice(a.workload, a.storage, a.steps, a.warmup, a.kernel)
+    m = run_lattice(a.workload, a.storage, a.steps, a.warmup, a.kernel, repeats=a.repeats)
     p, nodes, achieved = m["p"], m["nodes"], m["achieved"]
     traffic = measured_traffic(a.workload, a.storage) if a.kernel == "fused" else None
     variants = {}
@@ -374,6 +388,11 @@ def main():
                      "kernel_ms_spread": m["kernel_ms_spread"],
                      "copy_ceiling": copy["gbps"] if copy else None,
                      "frac_of_copy_ceiling": achieved / copy["gbps"] if (copy and achieved) else None},
+        "repeat_runs": ({"glups": [m["glups"]] + m["repeats"],
+                         "median_glups": float(statistics.median([m["glups"]] + m["repeats"])),
+                         "note": "the timed region (value) and %d further runs of the same number of steps on the same "
+                                 "lattice right after it, each by the wall clock around it" % len(m["repeats"])}
+                        if m["repeats"] else None),
         "busy_state": busy,
         "storage_variants": variants,
         "secondary": secondary,
