@@ -27,7 +27,7 @@ CS2 = 1.0 / 3.0
 BOUND = {"fp16": 2.5e-2, "bf16": 2.0e-1}
 # the 2000-step jets against binary32: relative L2 of u_z and phi, and the relative change of the
 # penetration length and of the axis-mean u_z (the chaotic divergence included)
-# (measured at We 10/100/2000: L2 of u_z and phi up to 2.3e-3 and 1.2e-2 for FP16, 2.1e-5 and 1.7e-4 for
+# (measured at We 10/100/2000: L2 of u_z and phi up to 2.3e-3 and 1.2e-2 for FP16, 3.2e-5 and 2.0e-4 for
 # FP16Q, 0.28 and 0.44 for BF16; penetration and axis-mean u_z unchanged with FP16 and FP16Q, 4-11 % lower
 # with BF16)
 L2_BOUND = {"fp16": 0.05, "fp16q": 1e-3, "bf16": 0.8}
@@ -124,7 +124,7 @@ def _l2(a, b):
 
 # the 128 x 128 x 512 jet (We = 100) after 200 steps from rest, worst field against binary32 (the
 # flow is still laminar: the difference is the storage rounding, not chaos).  FP16Q: the 1e-3 target
-# (measured 9.0e-4); FP16 measured 1.1e-2, BF16 1.2e-1
+# (measured 9.3e-4); FP16 measured 1.4e-2, BF16 1.1e-1
 SHORT_BOUND = {"fp16q": 1e-3, "fp16": 2.5e-2, "bf16": 2.0e-1}
 
 
